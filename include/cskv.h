@@ -1,0 +1,187 @@
+/*
+ * cskv.h - C interface of an MI355X-native cache-semantic GPU hash table.
+ *
+ * The table follows arxiv 2603.17168 ("HierarchicalKV"): u64 keys with u64 scores in
+ * buckets of 128 slots (Sec. 3.2), each bucket stored as a 128-byte digest line plus key and
+ * score lines; value rows of `dim` fp32 stored apart from the keys and addressed by
+ * (bucket, slot) (Sec. 3.6, position-based addressing).  A full bucket is resolved in place by
+ * evicting its lowest-score entry or by refusing admission (Sec. 3.3, Alg. 2); each key has two
+ * candidate buckets chosen by load, then by score (Sec. 3.4, Alg. 3).  The API mirrors the
+ * paper's batched STL-style interface (Sec. 4.1): every call processes a batch of keys with a
+ * sequence of kernels enqueued on the caller's stream.
+ *
+ * Conventions that hold for every call:
+ *  - Pointers named d_* are device pointers owned by the caller.  The library never allocates,
+ *    frees or keeps them after the call returns.  Table storage and workspaces are caller
+ *    memory too (e.g. a torch uint8 tensor).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are asynchronous and ordered
+ *    on that stream; outputs are valid once the stream has reached the end of the call.  One
+ *    table must be used from one stream at a time (or with the caller ordering the streams).
+ *  - Argument errors are returned synchronously and nothing is enqueued.  A failed kernel
+ *    launch returns CSKV_EHIP.  Problems with single keys (reserved words) are reported as
+ *    per-key statuses, not as call errors.
+ *  - n = 0 is a valid no-op (no clock tick, no kernel).
+ *  - Reserved key words: 0 marks an empty slot and 2^64-1 a locked slot; neither is a valid
+ *    user key (status CSKV_ST_INVALID_KEY; find reports not found; erase reports not erased).
+ *  - Value rows are float32[dim]; dim must be a multiple of 4 in [4, 1024].  d_values pointers
+ *    must be 16-byte aligned; key, score and count pointers 8-byte aligned.
+ *  - Output buffers must not alias table storage or one another.
+ *
+ * Batch semantics of an upsert call (insert_or_assign / insert_and_evict):
+ *  1. Scores: CUSTOM takes d_scores[i]; LRU gives every key of the call the table clock,
+ *     which advances by one per call; LFU adds d_scores[i] (1 if d_scores is NULL) per
+ *     occurrence, saturating at 2^64-1, to the key's score (0 for a new key).
+ *  2. Duplicate keys collapse to one operation; the last occurrence provides the value row
+ *     (and the CUSTOM score); every occurrence gets that operation's status.
+ *  3. Routing reads the table as it was before the call: a key present in one of its
+ *     candidates is updated in place; otherwise single mode (or equal candidates) targets b1,
+ *     dual mode targets the less occupied candidate while either has a free slot (b1 on a
+ *     tie, phase D1) and else the candidate whose minimum (score, key) entry is smaller
+ *     (phase D2).
+ *  4. Per bucket, updates first; then inserts in (score descending, key ascending) order:
+ *     a free slot takes the key; else the minimum (score, key) entry is evicted if the new
+ *     score is strictly greater than its score, otherwise the key is rejected.
+ * The result (statuses, evicted set, table contents per bucket) is deterministic and equals
+ * the sequential CPU definition; slot positions inside a bucket and the order of evicted
+ * entries in the output are not part of the result.
+ */
+#ifndef CSKV_H
+#define CSKV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cskv_table cskv_table;
+
+/* return codes */
+enum {
+    CSKV_OK = 0,
+    CSKV_EINVAL = -1,      /* bad argument (null, misaligned, out of range) */
+    CSKV_ENOMEM = -2,      /* storage or workspace smaller than required */
+    CSKV_EHIP = -3,        /* a HIP call or kernel launch failed */
+    CSKV_EUNSUPPORTED = -4 /* valid but unsupported configuration */
+};
+
+/* table modes (Sec. 3.2 single-bucket confinement; Sec. 3.4 dual-bucket selection) */
+enum { CSKV_MODE_SINGLE = 1, CSKV_MODE_DUAL = 2 };
+
+/* score policies (Sec. 3.3 "scoring policies") */
+enum { CSKV_SCORE_CUSTOM = 0, CSKV_SCORE_LRU = 1, CSKV_SCORE_LFU = 2 };
+
+/* per-key statuses of upserts (Alg. 2 outcomes) */
+enum {
+    CSKV_ST_UPDATED = 1,
+    CSKV_ST_INSERTED = 2,
+    CSKV_ST_INSERTED_EVICT = 3,
+    CSKV_ST_REJECTED = 4,
+    CSKV_ST_INVALID_KEY = 5
+};
+
+/* operation ids for cskv_workspace_bytes */
+enum { CSKV_OP_FIND = 0, CSKV_OP_INSERT_OR_ASSIGN = 1, CSKV_OP_INSERT_AND_EVICT = 2, CSKV_OP_ERASE = 3 };
+
+/*
+ * Bytes of device storage a table needs (Sec. 3.2 bucket layout, Sec. 3.6 value store):
+ * per bucket a 128-B digest line, 128 keys, 128 scores, 128 value rows, plus 9 B of per-bucket
+ * bookkeeping.  capacity must be 128 * B with B a power of two, 1 <= B <= 2^24; bucket_size
+ * must be 128.  Returns 0 if the arguments are invalid.
+ */
+size_t cskv_table_bytes(uint64_t capacity, uint32_t bucket_size, uint32_t dim);
+
+/*
+ * Creates a table over caller storage d_storage (>= cskv_table_bytes, 256-byte aligned) and
+ * enqueues on `stream` the kernel that empties it.  The host object *out is freed by
+ * cskv_destroy; the storage stays the caller's.  mode: CSKV_MODE_*; score_policy: CSKV_SCORE_*.
+ * Errors: CSKV_EINVAL (null out/storage, bad mode/policy/dim, misaligned storage),
+ * CSKV_EUNSUPPORTED (bucket_size != 128), CSKV_ENOMEM (storage too small), CSKV_EHIP.
+ */
+int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
+                int score_policy, void* d_storage, size_t storage_bytes, void* stream);
+
+/* Frees the host object (never the storage).  NULL is accepted. */
+int cskv_destroy(cskv_table* table);
+
+/* Empties the table (all slots free) on `stream`; the LRU clock is kept. */
+int cskv_clear(cskv_table* table, void* stream);
+
+/*
+ * Bytes of device workspace an operation on n keys needs (CSKV_OP_*); 0 for find.  The
+ * workspace is scratch for one call: its contents on entry are ignored.  Must be 256-byte
+ * aligned.  Returns 0 for an unknown op.
+ */
+size_t cskv_workspace_bytes(const cskv_table* table, int op, uint64_t n);
+
+/*
+ * find (Alg. 1, digest-accelerated lookup; dual mode probes b2 after a miss in b1).
+ * d_keys[n] in; d_values_out[n*dim] gets the row of every found key, rows of missing keys are
+ * left untouched; d_found[n] (u8) gets 1/0; d_scores_out[n] (nullable) gets the score of every
+ * found key.  No table state changes.
+ */
+int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_values_out,
+              uint8_t* d_found, uint64_t* d_scores_out, void* stream);
+
+/*
+ * insert_or_assign (Alg. 2 with Alg. 3's bucket choice; batch semantics above).
+ * d_keys[n], d_values[n*dim] in.  d_scores[n]: CUSTOM - required, the scores; LRU - ignored
+ * (may be NULL); LFU - increments, NULL means 1 each.  d_status[n] (nullable) gets CSKV_ST_*.
+ * d_ws: workspace of cskv_workspace_bytes(table, CSKV_OP_INSERT_OR_ASSIGN, n) bytes.
+ */
+int cskv_insert_or_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                          const uint64_t* d_scores, uint8_t* d_status, void* d_ws, size_t ws_bytes,
+                          void* stream);
+
+/*
+ * insert_and_evict (Sec. 4.1: insert_or_assign that also returns what it evicted).
+ * Same inputs as insert_or_assign; d_status is required.  Every entry displaced by the call
+ * is written to d_ev_keys[j], d_ev_scores[j] (the score it had, after any update in the same
+ * call) and d_ev_values[j*dim..] for j < *d_n_evicted (a device u64 written by the call; at
+ * most n).  Output order is unspecified.  Rejected incoming keys are not in the evicted list.
+ */
+int cskv_insert_and_evict(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                          const uint64_t* d_scores, uint8_t* d_status, uint64_t* d_ev_keys,
+                          float* d_ev_values, uint64_t* d_ev_scores, uint64_t* d_n_evicted, void* d_ws,
+                          size_t ws_bytes, void* stream);
+
+/*
+ * erase (inserter-group call of Sec. 3.5): removes every present key.  d_erased[n] (nullable)
+ * gets 1 if key i was present before the call (duplicates all report 1), else 0.
+ * d_ws: cskv_workspace_bytes(table, CSKV_OP_ERASE, n) bytes.
+ */
+int cskv_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws,
+               size_t ws_bytes, void* stream);
+
+/* size (reader-group call of Sec. 3.5): number of occupied slots, written to device u64 *d_size. */
+int cskv_size(cskv_table* table, uint64_t* d_size, void* stream);
+
+/*
+ * export (Sec. 4.1's export for checkpointing, without a predicate): every entry of buckets
+ * [bucket_begin, bucket_end) is written to d_keys[j], d_scores[j], d_values[j*dim..] and, if
+ * d_slots is not NULL, its slot index bucket*128+slot to d_slots[j], for j < *d_count (device
+ * u64).  Output capacity must be (bucket_end - bucket_begin) * 128.  Order unspecified.
+ * d_values and d_scores may be NULL.
+ */
+int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t* d_keys,
+                float* d_values, uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count, void* stream);
+
+/* LRU logical clock (number of non-empty upsert calls so far, plus any value set below). */
+uint64_t cskv_clock(const cskv_table* table);
+int cskv_set_clock(cskv_table* table, uint64_t clock);
+
+/* number of buckets, value dim, mode and policy of a table (0 / -1 for NULL) */
+uint64_t cskv_num_buckets(const cskv_table* table);
+uint32_t cskv_dim(const cskv_table* table);
+int cskv_mode(const cskv_table* table);
+int cskv_policy(const cskv_table* table);
+
+/* static text for a return code */
+const char* cskv_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSKV_H */

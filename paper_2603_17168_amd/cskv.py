@@ -1,0 +1,237 @@
+"""Python binding of the cskv C-ABI (include/cskv.h): argument marshalling over torch tensors.
+
+Every step of every call runs in the HIP library ``libcskv.so``; this module only allocates
+device tensors (table storage, workspaces, outputs) with torch, passes their pointers and the
+current HIP stream, and turns return codes into exceptions.  If the library is missing the
+import of :class:`Table` fails loudly: there is no fallback.
+
+Keys and scores are 64-bit words carried in torch.int64 (or torch.uint64) tensors; values are
+float32 [n, dim] tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcskv.so")
+
+MODE = {"single": 1, "dual": 2}
+POLICY = {"custom": 0, "lru": 1, "lfu": 2}
+OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE = 0, 1, 2, 3
+ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
+
+_lib = None
+
+
+class CskvError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libcskv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CskvError(f"{LIB_PATH} is missing: build it with paper_2603_17168_amd/build.py "
+                        "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P, U64, U32, I, SZ = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "cskv_table_bytes": (SZ, [U64, U32, U32]),
+        "cskv_create": (I, [ctypes.POINTER(P), U64, U32, U32, I, I, P, SZ, P]),
+        "cskv_destroy": (I, [P]),
+        "cskv_clear": (I, [P, P]),
+        "cskv_workspace_bytes": (SZ, [P, I, U64]),
+        "cskv_find": (I, [P, U64, P, P, P, P, P]),
+        "cskv_insert_or_assign": (I, [P, U64, P, P, P, P, P, SZ, P]),
+        "cskv_insert_and_evict": (I, [P, U64, P, P, P, P, P, P, P, P, P, SZ, P]),
+        "cskv_erase": (I, [P, U64, P, P, P, SZ, P]),
+        "cskv_size": (I, [P, P, P]),
+        "cskv_export": (I, [P, U64, U64, P, P, P, P, P, P]),
+        "cskv_clock": (U64, [P]),
+        "cskv_set_clock": (I, [P, U64]),
+        "cskv_num_buckets": (U64, [P]),
+        "cskv_dim": (U32, [P]),
+        "cskv_mode": (I, [P]),
+        "cskv_policy": (I, [P]),
+        "cskv_strerror": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise CskvError(f"{what}: {lib().cskv_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _as_i64(t: torch.Tensor, device) -> torch.Tensor:
+    if t.dtype == torch.uint64:
+        t = t.view(torch.int64)
+    if t.dtype != torch.int64:
+        raise TypeError("keys/scores must be int64 or uint64 tensors (64-bit words)")
+    if t.device != device:
+        raise ValueError(f"tensor on {t.device}, table on {device}")
+    return t.contiguous()
+
+
+class Table:
+    """A cache-semantic hash table in device memory (one caller-visible storage tensor)."""
+
+    def __init__(self, capacity: int, dim: int, mode: str = "dual", policy: str = "lru",
+                 device="cuda", bucket_size: int = 128):
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the table lives in GPU memory")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        L = lib()
+        nbytes = int(L.cskv_table_bytes(capacity, bucket_size, dim))
+        if nbytes == 0:
+            raise CskvError(f"invalid table geometry capacity={capacity} bucket_size={bucket_size} dim={dim}")
+        self.capacity, self.dim, self.bucket_size = int(capacity), int(dim), int(bucket_size)
+        self.mode, self.policy = mode, policy
+        self.n_buckets = self.capacity // self.bucket_size
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.cskv_create(ctypes.byref(h), capacity, bucket_size, dim, MODE[mode], POLICY[policy],
+                                 _ptr(self.storage), nbytes, _stream(self.device)), "cskv_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cskv_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------ helpers
+    def workspace(self, op: int, n: int) -> torch.Tensor:
+        need = int(lib().cskv_workspace_bytes(self._h, op, n))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _vals(self, v: torch.Tensor, n: int) -> torch.Tensor:
+        if v.dtype != torch.float32 or v.device != self.device:
+            raise TypeError("values must be float32 on the table's device")
+        v = v.contiguous()
+        if v.numel() != n * self.dim:
+            raise ValueError(f"values must hold n*dim = {n * self.dim} floats")
+        return v
+
+    # ------------------------------------------------------------------ API
+    @property
+    def clock(self) -> int:
+        return int(lib().cskv_clock(self._h))
+
+    @clock.setter
+    def clock(self, c: int):
+        _check(lib().cskv_set_clock(self._h, c), "cskv_set_clock")
+
+    def clear(self):
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_clear(self._h, _stream(self.device)), "cskv_clear")
+
+    def find(self, keys: torch.Tensor, values_out=None, found_out=None, scores_out=None, want_scores=True):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        if values_out is None:
+            values_out = torch.zeros((n, self.dim), dtype=torch.float32, device=self.device)
+        if found_out is None:
+            found_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        if scores_out is None and want_scores:
+            scores_out = torch.zeros(n, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_find(self._h, n, _ptr(keys), _ptr(values_out), _ptr(found_out), _ptr(scores_out),
+                                   _stream(self.device)), "cskv_find")
+        return values_out, found_out, scores_out
+
+    def insert_or_assign(self, keys, values, scores=None, status_out=None, want_status=True):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        values = self._vals(values, n)
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if status_out is None and want_status:
+            status_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(OP_INSERT_OR_ASSIGN, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_insert_or_assign(self._h, n, _ptr(keys), _ptr(values), _ptr(scores), _ptr(status_out),
+                                               _ptr(ws), ws.numel(), _stream(self.device)), "cskv_insert_or_assign")
+        return status_out
+
+    def insert_and_evict(self, keys, values, scores=None, out=None):
+        """Returns (status, ev_keys, ev_values, ev_scores, n_evicted_device_tensor); the first
+        n_evicted rows of the ev_* tensors are valid."""
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        values = self._vals(values, n)
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if out is None:
+            out = (torch.empty(n, dtype=torch.uint8, device=self.device),
+                   torch.empty(max(n, 1), dtype=torch.int64, device=self.device),
+                   torch.empty((max(n, 1), self.dim), dtype=torch.float32, device=self.device),
+                   torch.empty(max(n, 1), dtype=torch.int64, device=self.device),
+                   torch.zeros(1, dtype=torch.int64, device=self.device))
+        status, ek, evv, es, cnt = out
+        ws = self.workspace(OP_INSERT_AND_EVICT, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_insert_and_evict(self._h, n, _ptr(keys), _ptr(values), _ptr(scores), _ptr(status),
+                                               _ptr(ek), _ptr(evv), _ptr(es), _ptr(cnt), _ptr(ws), ws.numel(),
+                                               _stream(self.device)), "cskv_insert_and_evict")
+        return status, ek, evv, es, cnt
+
+    def erase(self, keys, erased_out=None, want_erased=True):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        if erased_out is None and want_erased:
+            erased_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(OP_ERASE, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_erase(self._h, n, _ptr(keys), _ptr(erased_out), _ptr(ws), ws.numel(),
+                                    _stream(self.device)), "cskv_erase")
+        return erased_out
+
+    def size_tensor(self, out=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_size(self._h, _ptr(out), _stream(self.device)), "cskv_size")
+        return out
+
+    def size(self) -> int:
+        return int(self.size_tensor().item())
+
+    def export(self, bucket_begin: int = 0, bucket_end: int | None = None, with_values: bool = True):
+        """(keys, values, scores, slots) of every entry in the bucket range (order unspecified)."""
+        b1 = self.n_buckets if bucket_end is None else bucket_end
+        cap = max(1, (b1 - bucket_begin) * self.bucket_size)
+        k = torch.empty(cap, dtype=torch.int64, device=self.device)
+        v = torch.empty((cap, self.dim), dtype=torch.float32, device=self.device) if with_values else None
+        s = torch.empty(cap, dtype=torch.int64, device=self.device)
+        sl = torch.empty(cap, dtype=torch.int64, device=self.device)
+        c = torch.zeros(1, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_export(self._h, bucket_begin, b1, _ptr(k), _ptr(v), _ptr(s), _ptr(sl), _ptr(c),
+                                     _stream(self.device)), "cskv_export")
+        n = int(c.item())
+        return k[:n], (v[:n] if v is not None else None), s[:n], sl[:n]

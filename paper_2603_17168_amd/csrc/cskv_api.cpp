@@ -1,0 +1,276 @@
+// C-ABI of the cache-semantic hash table: argument checks, storage and workspace layout,
+// kernel sequencing.  No allocation happens here: storage and workspaces belong to the caller.
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "../../include/cskv.h"
+#include "cskv_internal.h"
+
+struct cskv_table {
+    cskv::TableView view;
+    uint64_t capacity;
+    uint64_t clock;
+    int mode;
+    int policy;
+    int group;  // lanes per key for probe kernels
+};
+
+namespace cskv {
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+StorageLayout storage_layout(uint64_t nb, uint32_t dim) {
+    StorageLayout L;
+    size_t o = 0;
+    L.off_dig = o;    o = align256(o + nb * kSlots);
+    L.off_keys = o;   o = align256(o + nb * kSlots * 8);
+    L.off_scores = o; o = align256(o + nb * kSlots * 8);
+    L.off_vals = o;   o = align256(o + nb * kSlots * (size_t)dim * 4);
+    L.off_cnt = o;    o = align256(o + nb * 4);
+    L.off_cbase = o;  o = align256(o + nb * 4);
+    L.off_freeb = o;  o = align256(o + nb);
+    L.total = o;
+    return L;
+}
+
+UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
+    UpsertLayout L;
+    uint64_t P = 64;
+    int logP = 6;
+    while (P < 2 * n) {
+        P <<= 1;
+        ++logP;
+    }
+    L.P = P;
+    L.logP = logP;
+    const uint64_t ncl = n < nb ? n : nb;
+    size_t o = 0;
+    L.off_skeys = o;    o = align256(o + P * 8);
+    L.off_slast = o;    o = align256(o + P * 4);
+    L.off_sinc = o;     o = align256(o + P * 8);
+    L.off_ssat = o;     o = align256(o + P * 4);
+    L.off_sstat = o;    o = align256(o + P);
+    L.off_slot_of = o;  o = align256(o + n * 4);
+    L.off_op_kind = o;  o = align256(o + n);
+    L.off_op_tgt = o;   o = align256(o + n * 4);
+    L.off_op_aux = o;   o = align256(o + n * 4);
+    L.off_op_score = o; o = align256(o + n * 8);
+    L.off_glist = o;    o = align256(o + n * 4);
+    L.off_clist = o;    o = align256(o + ncl * 4);
+    L.off_ctr = o;      o = align256(o + 64 * 4);
+    L.total = o;
+    return L;
+}
+
+size_t erase_ws_bytes(uint64_t n) { return align256(n * 4); }
+
+}  // namespace cskv
+
+using namespace cskv;
+
+static inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+static inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+static inline int hip_rc(hipError_t e) { return e == hipSuccess ? CSKV_OK : CSKV_EHIP; }
+
+static bool valid_geometry(uint64_t capacity, uint32_t bucket_size, uint32_t dim, uint64_t* nb_out) {
+    if (bucket_size != (uint32_t)kSlots) return false;
+    if (capacity == 0 || capacity % kSlots) return false;
+    const uint64_t nb = capacity / kSlots;
+    if (nb & (nb - 1)) return false;
+    if (nb > (1ull << 24)) return false;
+    if (dim < 4 || dim > 1024 || (dim & 3)) return false;
+    *nb_out = nb;
+    return true;
+}
+
+extern "C" {
+
+size_t cskv_table_bytes(uint64_t capacity, uint32_t bucket_size, uint32_t dim) {
+    uint64_t nb;
+    if (!valid_geometry(capacity, bucket_size, dim, &nb)) return 0;
+    return storage_layout(nb, dim).total;
+}
+
+int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
+                int score_policy, void* d_storage, size_t storage_bytes, void* stream) {
+    if (!out || !d_storage) return CSKV_EINVAL;
+    *out = nullptr;
+    if (mode != CSKV_MODE_SINGLE && mode != CSKV_MODE_DUAL) return CSKV_EINVAL;
+    if (score_policy != CSKV_SCORE_CUSTOM && score_policy != CSKV_SCORE_LRU && score_policy != CSKV_SCORE_LFU)
+        return CSKV_EINVAL;
+    if (bucket_size != (uint32_t)kSlots) return CSKV_EUNSUPPORTED;
+    uint64_t nb;
+    if (!valid_geometry(capacity, bucket_size, dim, &nb)) return CSKV_EINVAL;
+    if (!aligned(d_storage, 256)) return CSKV_EINVAL;
+    const StorageLayout L = storage_layout(nb, dim);
+    if (storage_bytes < L.total) return CSKV_ENOMEM;
+    cskv_table* t = new (std::nothrow) cskv_table;
+    if (!t) return CSKV_ENOMEM;
+    uint8_t* base = reinterpret_cast<uint8_t*>(d_storage);
+    t->view.dig = base + L.off_dig;
+    t->view.keys = reinterpret_cast<uint64_t*>(base + L.off_keys);
+    t->view.scores = reinterpret_cast<uint64_t*>(base + L.off_scores);
+    t->view.vals = reinterpret_cast<float*>(base + L.off_vals);
+    t->view.cnt = reinterpret_cast<uint32_t*>(base + L.off_cnt);
+    t->view.cbase = reinterpret_cast<uint32_t*>(base + L.off_cbase);
+    t->view.freeb = base + L.off_freeb;
+    t->view.nbuckets = nb;
+    t->view.bmask = (uint32_t)(nb - 1);
+    t->view.dim = dim;
+    t->view.dual = (mode == CSKV_MODE_DUAL);
+    t->view.policy = score_policy;
+    t->capacity = capacity;
+    t->clock = 0;
+    t->mode = mode;
+    t->policy = score_policy;
+    t->group = 8;
+    const int rc = hip_rc(launch_clear_table(t->view, as_stream(stream)));
+    if (rc != CSKV_OK) {
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return CSKV_OK;
+}
+
+int cskv_destroy(cskv_table* table) {
+    delete table;
+    return CSKV_OK;
+}
+
+int cskv_clear(cskv_table* table, void* stream) {
+    if (!table) return CSKV_EINVAL;
+    return hip_rc(launch_clear_table(table->view, as_stream(stream)));
+}
+
+size_t cskv_workspace_bytes(const cskv_table* table, int op, uint64_t n) {
+    if (!table) return 0;
+    switch (op) {
+        case CSKV_OP_FIND: return 0;
+        case CSKV_OP_INSERT_OR_ASSIGN:
+        case CSKV_OP_INSERT_AND_EVICT: return upsert_layout(n, table->view.nbuckets).total;
+        case CSKV_OP_ERASE: return erase_ws_bytes(n);
+        default: return 0;
+    }
+}
+
+static bool n_ok(uint64_t n) { return n < (1ull << 31); }
+
+int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_values_out, uint8_t* d_found,
+              uint64_t* d_scores_out, void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_values_out || !d_found) return CSKV_EINVAL;
+    if (!aligned(d_keys, 8) || !aligned(d_values_out, 16) || (d_scores_out && !aligned(d_scores_out, 8)))
+        return CSKV_EINVAL;
+    return hip_rc(launch_find(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
+                              as_stream(stream)));
+}
+
+static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                         const uint64_t* d_scores, uint8_t* d_status, const EvictOut& ev, void* d_ws,
+                         size_t ws_bytes, void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_values || !d_ws) return CSKV_EINVAL;
+    if (table->policy == CSKV_SCORE_CUSTOM && !d_scores) return CSKV_EINVAL;
+    if (!aligned(d_keys, 8) || !aligned(d_values, 16) || !aligned(d_ws, 256) || (d_scores && !aligned(d_scores, 8)))
+        return CSKV_EINVAL;
+    const UpsertLayout L = upsert_layout(n, table->view.nbuckets);
+    if (ws_bytes < L.total) return CSKV_ENOMEM;
+    uint8_t* b = reinterpret_cast<uint8_t*>(d_ws);
+    UpsertWs w;
+    w.skeys = reinterpret_cast<uint64_t*>(b + L.off_skeys);
+    w.slast = reinterpret_cast<uint32_t*>(b + L.off_slast);
+    w.sinc = reinterpret_cast<uint64_t*>(b + L.off_sinc);
+    w.ssat = reinterpret_cast<uint32_t*>(b + L.off_ssat);
+    w.sstat = b + L.off_sstat;
+    w.slot_of = reinterpret_cast<uint32_t*>(b + L.off_slot_of);
+    w.op_kind = b + L.off_op_kind;
+    w.op_tgt = reinterpret_cast<uint32_t*>(b + L.off_op_tgt);
+    w.op_aux = reinterpret_cast<uint32_t*>(b + L.off_op_aux);
+    w.op_score = reinterpret_cast<uint64_t*>(b + L.off_op_score);
+    w.glist = reinterpret_cast<uint32_t*>(b + L.off_glist);
+    w.clist = reinterpret_cast<uint32_t*>(b + L.off_clist);
+    w.ctr = reinterpret_cast<uint32_t*>(b + L.off_ctr);
+    w.P = L.P;
+    w.logP = L.logP;
+    uint64_t clock = table->clock;
+    if (table->policy == CSKV_SCORE_LRU) clock += 1;
+    const int rc = hip_rc(launch_upsert(table->view, w, n, d_keys, d_values, d_scores, d_status, ev, clock,
+                                        table->group, as_stream(stream)));
+    if (rc == CSKV_OK) table->clock = clock;
+    return rc;
+}
+
+int cskv_insert_or_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                          const uint64_t* d_scores, uint8_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
+    EvictOut ev{nullptr, nullptr, nullptr, nullptr};
+    return upsert_common(table, n, d_keys, d_values, d_scores, d_status, ev, d_ws, ws_bytes, stream);
+}
+
+int cskv_insert_and_evict(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                          const uint64_t* d_scores, uint8_t* d_status, uint64_t* d_ev_keys, float* d_ev_values,
+                          uint64_t* d_ev_scores, uint64_t* d_n_evicted, void* d_ws, size_t ws_bytes,
+                          void* stream) {
+    if (!table) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_status || !d_ev_keys || !d_ev_values || !d_ev_scores || !d_n_evicted) return CSKV_EINVAL;
+    if (!aligned(d_ev_keys, 8) || !aligned(d_ev_values, 16) || !aligned(d_ev_scores, 8) || !aligned(d_n_evicted, 8))
+        return CSKV_EINVAL;
+    EvictOut ev{d_ev_keys, d_ev_values, d_ev_scores, d_n_evicted};
+    return upsert_common(table, n, d_keys, d_values, d_scores, d_status, ev, d_ws, ws_bytes, stream);
+}
+
+int cskv_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws, size_t ws_bytes,
+               void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_ws || !aligned(d_keys, 8) || !aligned(d_ws, 256)) return CSKV_EINVAL;
+    if (ws_bytes < erase_ws_bytes(n)) return CSKV_ENOMEM;
+    return hip_rc(launch_erase(table->view, n, d_keys, d_erased, reinterpret_cast<uint32_t*>(d_ws), table->group,
+                               as_stream(stream)));
+}
+
+int cskv_size(cskv_table* table, uint64_t* d_size, void* stream) {
+    if (!table || !d_size || !aligned(d_size, 8)) return CSKV_EINVAL;
+    return hip_rc(launch_size(table->view, d_size, as_stream(stream)));
+}
+
+int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t* d_keys, float* d_values,
+                uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count, void* stream) {
+    if (!table || !d_keys || !d_count) return CSKV_EINVAL;
+    if (bucket_begin > bucket_end || bucket_end > table->view.nbuckets) return CSKV_EINVAL;
+    if (!aligned(d_keys, 8) || !aligned(d_count, 8) || (d_values && !aligned(d_values, 16)) ||
+        (d_scores && !aligned(d_scores, 8)) || (d_slots && !aligned(d_slots, 8)))
+        return CSKV_EINVAL;
+    return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
+                                as_stream(stream)));
+}
+
+uint64_t cskv_clock(const cskv_table* table) { return table ? table->clock : 0; }
+
+int cskv_set_clock(cskv_table* table, uint64_t clock) {
+    if (!table) return CSKV_EINVAL;
+    table->clock = clock;
+    return CSKV_OK;
+}
+
+uint64_t cskv_num_buckets(const cskv_table* table) { return table ? table->view.nbuckets : 0; }
+uint32_t cskv_dim(const cskv_table* table) { return table ? table->view.dim : 0; }
+int cskv_mode(const cskv_table* table) { return table ? table->mode : -1; }
+int cskv_policy(const cskv_table* table) { return table ? table->policy : -1; }
+
+const char* cskv_strerror(int code) {
+    switch (code) {
+        case CSKV_OK: return "ok";
+        case CSKV_EINVAL: return "invalid argument";
+        case CSKV_ENOMEM: return "storage or workspace too small";
+        case CSKV_EHIP: return "HIP error";
+        case CSKV_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

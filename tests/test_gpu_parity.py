@@ -1,0 +1,197 @@
+"""GPU parity: the HIP table, called through the C-ABI, against the sequential oracle, bit for bit
+(statuses, found masks, rows, scores, evicted sets, per-bucket table contents)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_17168_amd import cskv
+from paper_2603_17168_amd.workload import as_u64, keys as gen_keys, randint, uniform_u64
+from tests.hashkeys import key_for
+from tests.parity import Twin
+
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def np_keys(stream, n, start=0):
+    return as_u64(gen_keys(stream, n, start))
+
+
+def test_c1_config_full_flow():
+    """Plain table, 2^18 slots (2048 x 128), dim 8, CUSTOM score = batch step: 16 insert batches
+    of 2^14 fresh keys to full load, a 2^16-key find at 50 % hit, 4 more insert_and_evict
+    batches past capacity; a twin run with insert_or_assign must end in the same table."""
+    say("c1: capacity 2^18 dim 8 dual custom")
+    tw = Twin(1 << 18, 8, "dual", "custom", seed=1)
+    twin2 = Twin(1 << 18, 8, "dual", "custom", seed=1)
+    bs = 1 << 14
+    for t in range(1, 17):
+        k = np_keys(1, bs, (t - 1) * bs)
+        sc = np.full(bs, t, dtype=np.uint64)
+        tw.upsert(k, sc)
+        twin2.upsert(k, sc)
+        tw.check_table()
+    say("c1: size", tw.ora.size())
+    resident = tw.ora.export()[0]
+    rng = np.random.default_rng(2)
+    hit = rng.choice(resident, 1 << 15, replace=False)
+    miss = np_keys(2, 1 << 15)
+    q = np.concatenate([hit, miss])[rng.permutation(1 << 16)]
+    of = tw.find(q)
+    assert of.sum() == 1 << 15
+    for t in range(17, 21):
+        k = np_keys(1, bs, (t - 1) * bs)
+        sc = np.full(bs, t, dtype=np.uint64)
+        tw.upsert(k, sc, evict=True)
+        twin2.upsert(k, sc, evict=False)
+        tw.check_table()
+    twin2.check_table()
+
+
+@pytest.mark.parametrize("mode", ["single", "dual"])
+@pytest.mark.parametrize("policy", ["custom", "lru", "lfu"])
+def test_random_mixed_small_tables(mode, policy):
+    """Random upsert / insert_and_evict / erase / find batches with duplicates and reserved
+    words on small tables that fill, overflow and drain; whole-table parity after each call."""
+    say(f"mixed: mode {mode} policy {policy}")
+    for seed, nb in [(1, 4), (2, 16), (3, 64)]:
+        rng = np.random.default_rng(seed * 100 + len(mode) + len(policy))
+        tw = Twin(nb * 128, 16, mode, policy, seed=seed)
+        universe = np_keys(10 + seed, nb * 128 * 3)
+        universe = np.concatenate([universe, np.array([0, M64], dtype=np.uint64)])
+        for step in range(24):
+            n = int(rng.integers(0, nb * 128))
+            k = rng.choice(universe, n)
+            r = rng.random()
+            if r < 0.6:
+                if policy == "custom":
+                    sc = rng.integers(0, 50, n).astype(np.uint64)
+                elif policy == "lfu":
+                    sc = rng.choice(np.array([1, 1, 2, 7], dtype=np.uint64), n) if rng.random() < 0.7 else None
+                else:
+                    sc = None
+                tw.upsert(k, sc, evict=bool(rng.random() < 0.5))
+            elif r < 0.8:
+                tw.erase(k)
+            else:
+                tw.find(k)
+            tw.check_table()
+
+
+def test_one_bucket_floods():
+    """Hundreds of distinct keys aimed at one bucket (b1 == b2): the bucket must keep exactly
+    the best 128 by (score, key), whatever the batch size (up to 3 selection chunks and beyond)."""
+    nb = 8
+    for m, seed in [(100, 1), (129, 2), (200, 3), (700, 4)]:
+        say(f"flood: {m} keys into bucket 3")
+        tw = Twin(nb * 128, 8, "dual", "custom", seed=seed)
+        rng = np.random.default_rng(seed)
+        k = np.array([key_for(3, 3, nb, salt=1 + i) for i in range(m)], dtype=np.uint64)
+        sc = rng.integers(0, 40, m).astype(np.uint64)
+        tw.upsert(k, sc)
+        tw.check_table()
+        k2 = np.array([key_for(3, 3, nb, salt=5000 + i) for i in range(m)], dtype=np.uint64)
+        tw.upsert(np.concatenate([k2, k[: m // 3]]), rng.integers(0, 60, m + m // 3).astype(np.uint64), evict=True)
+        tw.check_table()
+
+
+def test_digest_collisions_and_equal_candidates():
+    """Distinct keys with the same bucket and the same 8-bit digest, and keys whose two
+    candidates coincide, in single and dual tables."""
+    nb = 16
+    for mode in ["single", "dual"]:
+        say(f"digest collisions: {mode}")
+        tw = Twin(nb * 128, 8, mode, "custom", seed=7)
+        ks = [key_for(5, 5, nb, salt=1 + i, digest=0x33) for i in range(150)]
+        ks += [key_for(5, 9, nb, salt=900 + i, digest=0x33) for i in range(150)]
+        ks += [key_for(9, 5, nb, salt=1900 + i, digest=0x33) for i in range(60)]
+        k = np.array(ks, dtype=np.uint64)
+        rng = np.random.default_rng(1)
+        for rep in range(3):
+            sel = rng.permutation(k.size)[: 200]
+            tw.upsert(k[sel], rng.integers(0, 100, sel.size).astype(np.uint64), evict=True)
+            tw.check_table()
+            tw.find(k)
+        tw.erase(k[::3])
+        tw.check_table()
+        tw.find(k)
+
+
+def test_dual_phase_d2_full_tables():
+    """Fill every bucket, then stream fresh keys so that all routing is phase D2 with LRU
+    scores (many equal minima broken by key)."""
+    say("d2: lru full table")
+    nb = 64
+    tw = Twin(nb * 128, 8, "dual", "lru", seed=3)
+    k = np_keys(30, nb * 128 * 2)
+    for s in range(0, k.size, 1024):
+        tw.upsert(k[s:s + 1024])
+    tw.check_table()
+    for rep in range(6):
+        tw.upsert(np_keys(31, 3000, rep * 3000), evict=True)
+        tw.check_table()
+
+
+def test_lfu_zipf_like_duplicates():
+    """A few keys repeated thousands of times in one batch (LFU sums, last-writer rows)."""
+    say("lfu duplicates")
+    tw = Twin(32 * 128, 8, "dual", "lfu", seed=4)
+    rng = np.random.default_rng(5)
+    hot = np_keys(40, 50)
+    cold = np_keys(41, 6000)
+    for rep in range(4):
+        k = np.concatenate([rng.choice(hot, 20000), rng.choice(cold, 3000)])[rng.permutation(23000)]
+        tw.upsert(k, None, evict=True)
+        tw.check_table()
+    sat = np.array([(1 << 63), (1 << 63), 5], dtype=np.uint64)
+    tw.upsert(np.array([hot[0], hot[0], hot[1]], dtype=np.uint64), sat)
+    tw.check_table()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 65, 257, 4099])
+def test_ragged_batch_sizes(n):
+    tw = Twin(64 * 128, 12, "dual", "lru", seed=n)
+    k = np_keys(50, n)
+    tw.upsert(k, evict=True)
+    tw.find(np.concatenate([k, np_keys(51, n)]))
+    tw.erase(k[: (n + 1) // 2])
+    tw.check_table()
+    tw.upsert(np.zeros(0, dtype=np.uint64))  # empty batch: no-op, no clock tick
+    tw.check_table()
+
+
+@pytest.mark.parametrize("dim", [4, 8, 32, 64, 128, 132])
+def test_value_dims(dim):
+    say(f"dim {dim}")
+    tw = Twin(32 * 128, dim, "dual", "custom", seed=dim)
+    rng = np.random.default_rng(dim)
+    for rep in range(3):
+        k = np_keys(60, 6000, rep * 2000)
+        tw.upsert(k, rng.integers(0, 9, k.size).astype(np.uint64), evict=True)
+        tw.find(np_keys(60, 9000))
+    tw.check_table()
+
+
+def test_api_errors_on_gpu():
+    t = cskv.Table(128 * 16, 8, "dual", "custom")
+    k = torch.ones(4, dtype=torch.int64, device="cuda")
+    v = torch.zeros((4, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(cskv.CskvError):
+        t.insert_or_assign(k, v, None)  # CUSTOM needs scores
+    with pytest.raises(cskv.CskvError):
+        t.export(5, 3)
+    bad = torch.zeros(4 * 8 + 1, dtype=torch.float32, device="cuda")[1:].view(4, 8)  # misaligned rows
+    with pytest.raises(cskv.CskvError):
+        t.insert_or_assign(k, bad, k)
+    lib = cskv.lib()
+    assert lib.cskv_table_bytes(128 * 3, 128, 8) == 0  # 3 buckets: not a power of two
+    assert lib.cskv_table_bytes(128 * 4, 64, 8) == 0
+    assert lib.cskv_table_bytes(128 * 4, 128, 6) == 0
