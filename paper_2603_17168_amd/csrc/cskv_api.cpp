@@ -28,10 +28,18 @@ StorageLayout storage_layout(uint64_t nb, uint32_t dim) {
     L.off_scores = o; o = align256(o + nb * kSlots * 8);
     L.off_vals = o;   o = align256(o + nb * kSlots * (size_t)dim * 4);
     L.off_cnt = o;    o = align256(o + nb * 4);
-    L.off_cbase = o;  o = align256(o + nb * 4);
-    L.off_freeb = o;  o = align256(o + nb);
+    L.off_bmin = o;   o = align256(o + nb * 16);
     L.total = o;
     return L;
+}
+
+// per-bucket inline capacity: about mean + 5 sd + 3 operations per bucket (Poisson), 4..16
+static uint32_t inline_capacity(uint64_t n, uint64_t nb) {
+    const double mu = (double)n / (double)nb;
+    const double want = mu + 5.0 * __builtin_sqrt(mu) + 3.0;
+    uint32_t c = 4;
+    while (c < (uint32_t)kFastMax && (double)c < want) c <<= 1;
+    return c;
 }
 
 UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
@@ -44,21 +52,28 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     }
     L.P = P;
     L.logP = logP;
-    const uint64_t ncl = n < nb ? n : nb;
+    L.cap = inline_capacity(n, nb);
+    const uint64_t nl = nb * L.cap;
+    const uint64_t nslow = n < nb ? n : nb;
     size_t o = 0;
-    L.off_skeys = o;    o = align256(o + P * 8);
-    L.off_slast = o;    o = align256(o + P * 4);
-    L.off_sinc = o;     o = align256(o + P * 8);
-    L.off_ssat = o;     o = align256(o + P * 4);
-    L.off_sstat = o;    o = align256(o + P);
-    L.off_slot_of = o;  o = align256(o + n * 4);
-    L.off_op_kind = o;  o = align256(o + n);
-    L.off_op_tgt = o;   o = align256(o + n * 4);
-    L.off_op_aux = o;   o = align256(o + n * 4);
-    L.off_op_score = o; o = align256(o + n * 8);
-    L.off_glist = o;    o = align256(o + n * 4);
-    L.off_clist = o;    o = align256(o + ncl * 4);
-    L.off_ctr = o;      o = align256(o + 64 * 4);
+    // zeroed on every call: dedupe set, overflow keys, counters (and the LFU sums)
+    L.off_dd = o;      o = align256(o + P * sizeof(DedupeEntry));
+    L.off_okey = o;    o = align256(o + P * 8);
+    L.off_ctr = o;     o = align256(o + 64 * 4);
+    L.off_zero_end = o;
+    L.off_inc = o;     o = align256(o + P * 8);
+    L.off_zero_end_lfu = o;
+    L.off_sstat = o;   o = align256(o + P);
+    L.off_slot_of = o; o = align256(o + n * 4);
+    L.off_ik = o;      o = align256(o + nl * 8);
+    L.off_is = o;      o = align256(o + nl * 8);
+    L.off_iw = o;      o = align256(o + nl * 8);
+    L.off_islot = o;   o = align256(o + nl);
+    L.off_ok = o;      o = align256(o + P * 8);
+    L.off_os = o;      o = align256(o + P * 8);
+    L.off_ow = o;      o = align256(o + P * 8);
+    L.off_oslot = o;   o = align256(o + P);
+    L.off_slow = o;    o = align256(o + nslow * 4);
     L.total = o;
     return L;
 }
@@ -113,8 +128,7 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->view.scores = reinterpret_cast<uint64_t*>(base + L.off_scores);
     t->view.vals = reinterpret_cast<float*>(base + L.off_vals);
     t->view.cnt = reinterpret_cast<uint32_t*>(base + L.off_cnt);
-    t->view.cbase = reinterpret_cast<uint32_t*>(base + L.off_cbase);
-    t->view.freeb = base + L.off_freeb;
+    t->view.bmin = reinterpret_cast<uint64_t*>(base + L.off_bmin);
     t->view.nbuckets = nb;
     t->view.bmask = (uint32_t)(nb - 1);
     t->view.dim = dim;
@@ -181,24 +195,28 @@ static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, 
     if (ws_bytes < L.total) return CSKV_ENOMEM;
     uint8_t* b = reinterpret_cast<uint8_t*>(d_ws);
     UpsertWs w;
-    w.skeys = reinterpret_cast<uint64_t*>(b + L.off_skeys);
-    w.slast = reinterpret_cast<uint32_t*>(b + L.off_slast);
-    w.sinc = reinterpret_cast<uint64_t*>(b + L.off_sinc);
-    w.ssat = reinterpret_cast<uint32_t*>(b + L.off_ssat);
+    w.dd = reinterpret_cast<DedupeEntry*>(b + L.off_dd);
+    w.okey = reinterpret_cast<uint64_t*>(b + L.off_okey);
+    w.ctr = reinterpret_cast<uint32_t*>(b + L.off_ctr);
+    w.inc = reinterpret_cast<uint64_t*>(b + L.off_inc);
     w.sstat = b + L.off_sstat;
     w.slot_of = reinterpret_cast<uint32_t*>(b + L.off_slot_of);
-    w.op_kind = b + L.off_op_kind;
-    w.op_tgt = reinterpret_cast<uint32_t*>(b + L.off_op_tgt);
-    w.op_aux = reinterpret_cast<uint32_t*>(b + L.off_op_aux);
-    w.op_score = reinterpret_cast<uint64_t*>(b + L.off_op_score);
-    w.glist = reinterpret_cast<uint32_t*>(b + L.off_glist);
-    w.clist = reinterpret_cast<uint32_t*>(b + L.off_clist);
-    w.ctr = reinterpret_cast<uint32_t*>(b + L.off_ctr);
+    w.ik = reinterpret_cast<uint64_t*>(b + L.off_ik);
+    w.is = reinterpret_cast<uint64_t*>(b + L.off_is);
+    w.iw = reinterpret_cast<uint64_t*>(b + L.off_iw);
+    w.islot = b + L.off_islot;
+    w.ok = reinterpret_cast<uint64_t*>(b + L.off_ok);
+    w.os = reinterpret_cast<uint64_t*>(b + L.off_os);
+    w.ow = reinterpret_cast<uint64_t*>(b + L.off_ow);
+    w.oslot = b + L.off_oslot;
+    w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);
     w.P = L.P;
     w.logP = L.logP;
+    w.cap = L.cap;
+    const size_t zero_bytes = table->policy == CSKV_SCORE_LFU ? L.off_zero_end_lfu : L.off_zero_end;
     uint64_t clock = table->clock;
     if (table->policy == CSKV_SCORE_LRU) clock += 1;
-    const int rc = hip_rc(launch_upsert(table->view, w, n, d_keys, d_values, d_scores, d_status, ev, clock,
+    const int rc = hip_rc(launch_upsert(table->view, w, n, d_keys, d_values, d_scores, d_status, ev, clock, zero_bytes,
                                         table->group, as_stream(stream)));
     if (rc == CSKV_OK) table->clock = clock;
     return rc;

@@ -6,17 +6,17 @@
 //     keys   u64[B][128]          key line(s) per bucket (0 = empty)
 //     scores u64[B][128]          score line(s) per bucket
 //     vals   f32[B][128][dim]     value rows, addressed by (bucket, slot)
-//     cnt    u32[B]               inserts routed to a bucket by the running call (0 between calls)
-//     cbase  u32[B]               start of a contended bucket's incoming list in the workspace
-//     freeb  u8 [B]               free slots of a routed-to bucket when the call started
+//     cnt    u32[B]               operations routed to a bucket by the running call (0 between calls)
+//     bmin   u64[B][2]            (score, key) of a full bucket's minimum entry; key 0 = not known
 //
-//   upsert workspace (n keys, P = power of two >= 2n, each array 256-byte aligned):
-//     skeys u64[P], slast u32[P], sinc u64[P], ssat u32[P], sstat u8[P]   batch dedupe set
-//     slot_of u32[n]                                                       set slot of key i
-//     op_kind u8[n], op_tgt u32[n], op_aux u32[n], op_score u64[n]         routed operations
-//     glist u32[n]                                                         contended ops by bucket
-//     clist u32[min(n, B)]                                                 contended buckets
-//     ctr u32[64]                                                          counters
+//   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity):
+//     zeroed on entry: dd {key u64, last u32, sat u32}[P], okey u64[P], ctr u32[64], inc u64[P] (LFU)
+//     sstat u8[P]                      status of each distinct key's operation
+//     slot_of u32[n]                   dedupe slot of input i (or kNoSlot)
+//     ik, is, iw u64[B*C], islot u8[B*C]   per-bucket operation lists: key, new score,
+//                                      (dedupe slot << 32 | input position), slot (0xFF = insert)
+//     ok, os, ow u64[P], oslot u8[P]   the same for list positions >= C, hashed on (bucket, position)
+//     slow u32[min(n, B)]              buckets with more operations than the fast path takes
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,9 +27,10 @@ namespace cskv {
 
 constexpr int kSlots = 128;
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint8_t kInsertSlot = 0xFF;
+constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
-enum OpKind : uint8_t { kOpNone = 0, kOpUpdate = 1, kOpInsert = 2 };
-enum Counter { kCtrContended = 0, kCtrListFill = 1 };
+enum Counter { kCtrSlow = 0 };
 
 struct TableView {
     uint8_t* dig;
@@ -37,8 +38,7 @@ struct TableView {
     uint64_t* scores;
     float* vals;
     uint32_t* cnt;
-    uint32_t* cbase;
-    uint8_t* freeb;
+    uint64_t* bmin;
     uint64_t nbuckets;
     uint32_t bmask;  // nbuckets - 1
     uint32_t dim;
@@ -46,22 +46,27 @@ struct TableView {
     int policy;
 };
 
+struct DedupeEntry {
+    uint64_t key;
+    uint32_t last;  // index of the last occurrence + 1
+    uint32_t sat;   // LFU: the increment sum overflowed
+};
+
 struct UpsertWs {
-    uint64_t* skeys;
-    uint32_t* slast;
-    uint64_t* sinc;
-    uint32_t* ssat;
+    DedupeEntry* dd;
+    uint64_t* okey;
+    uint32_t* ctr;
+    uint64_t* inc;
     uint8_t* sstat;
     uint32_t* slot_of;
-    uint8_t* op_kind;
-    uint32_t* op_tgt;
-    uint32_t* op_aux;
-    uint64_t* op_score;
-    uint32_t* glist;
-    uint32_t* clist;
-    uint32_t* ctr;
+    uint64_t *ik, *is, *iw;
+    uint8_t* islot;
+    uint64_t *ok, *os, *ow;
+    uint8_t* oslot;
+    uint32_t* slow;
     uint64_t P;
     int logP;
+    uint32_t cap;  // inline operations per bucket
 };
 
 struct EvictOut {
@@ -72,14 +77,16 @@ struct EvictOut {
 };
 
 struct StorageLayout {
-    size_t off_dig, off_keys, off_scores, off_vals, off_cnt, off_cbase, off_freeb, total;
+    size_t off_dig, off_keys, off_scores, off_vals, off_cnt, off_bmin, total;
 };
 
 struct UpsertLayout {
-    size_t off_skeys, off_slast, off_sinc, off_ssat, off_sstat, off_slot_of, off_op_kind, off_op_tgt,
-        off_op_aux, off_op_score, off_glist, off_clist, off_ctr, total;
+    size_t off_dd, off_okey, off_ctr, off_inc, off_zero_end, off_zero_end_lfu;
+    size_t off_sstat, off_slot_of, off_ik, off_is, off_iw, off_islot, off_ok, off_os, off_ow, off_oslot, off_slow,
+        total;
     uint64_t P;
     int logP;
+    uint32_t cap;
 };
 
 StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim);
@@ -93,7 +100,7 @@ hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, flo
                        uint64_t* scores_out, int group, hipStream_t s);
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
                          const float* vals, const uint64_t* scores, uint8_t* status, const EvictOut& ev,
-                         uint64_t clock, int group, hipStream_t s);
+                         uint64_t clock, size_t zero_bytes, int group, hipStream_t s);
 hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                         uint32_t* ws_slot, int group, hipStream_t s);
 hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s);

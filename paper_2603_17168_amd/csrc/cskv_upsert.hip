@@ -1,0 +1,675 @@
+// Upsert kernels of the cache-semantic hash table (insert_or_assign / insert_and_evict) for
+// CDNA4 (gfx950, wave64): Alg. 2 (in-line upsert with admission control and eviction) inside
+// Alg. 3 (score-based dual-bucket choice), under the deterministic batch order of cskv.h.
+//
+// One call is a fixed sequence on one stream:
+//   zero     one fill of the call's scratch (dedupe set, overflow keys, counters)
+//   dedupe   one set entry per distinct key: last occurrence (atomicMax), LFU increment sum
+//   route    G lanes per distinct key, against the table as it was before the call: update slot
+//            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
+//            smaller cached bucket minimum (score, key)); the operation is appended to the
+//            target bucket's list (rank from an atomic count per bucket)
+//   apply    16 lanes per bucket (8 slots each), 64 buckets per 1024-thread block: updates,
+//            then inserts ranked by (score desc, key asc): the first ones take free slots, the
+//            rest compete with the smallest residents by (score, key) - strict admission;
+//            victims are copied out, slots written, the bucket minimum cached when full
+//   slow     one wave per bucket that received more than 16 operations: same rules, with the
+//            best 128 inserts kept in LDS
+//   finish   per-occurrence status
+// Every write to a table slot's key/score/digest is made by the lane that owns the slot, and
+// every 16-byte chunk c of a row by lane c mod (lanes), so writes that must follow one another
+// (an update, then the eviction of the same entry) are ordered by program order.
+#include <hip/hip_runtime.h>
+
+#include "cskv_device.h"
+#include "cskv_internal.h"
+
+namespace cskv {
+
+constexpr int GA = 16;            // lanes per bucket in the fast apply kernel
+constexpr int SPL = kSlots / GA;  // slots per lane
+constexpr uint64_t kGold = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t scratch_hash(uint64_t x, int logP) { return (fmix64(x) * kGold) >> (64 - logP); }
+
+__device__ __forceinline__ uint64_t overflow_key(uint32_t b, uint32_t r) { return ((uint64_t)b << 32) + r + 1; }
+
+struct Entry {
+    uint64_t key, score, w;  // w = dedupe slot << 32 | input position
+    uint8_t slot;            // kInsertSlot for an insert
+};
+
+// the r-th operation routed to bucket b
+__device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
+    Entry e;
+    if (r < w.cap) {
+        const size_t x = (size_t)b * w.cap + r;
+        e.key = w.ik[x];
+        e.score = w.is[x];
+        e.w = w.iw[x];
+        e.slot = w.islot[x];
+        return e;
+    }
+    const uint64_t ok = overflow_key(b, r);
+    uint64_t q = scratch_hash(ok, w.logP);
+    for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
+    e.key = w.ok[q];
+    e.score = w.os[q];
+    e.w = w.ow[q];
+    e.slot = w.oslot[q];
+    return e;
+}
+
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
+                                                const uint64_t* __restrict__ scores, uint64_t* ev_count) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && ev_count) *ev_count = 0;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    if (reserved_key(k)) {
+        w.slot_of[i] = kNoSlot;
+        return;
+    }
+    const uint64_t mask = w.P - 1;
+    uint64_t p = scratch_hash(k, w.logP);
+    for (uint64_t probes = 0; probes < w.P; ++probes) {
+        const uint64_t cur = w.dd[p].key;
+        if (cur == k) break;
+        if (cur == 0) {
+            const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[p].key), 0ull,
+                                                     (unsigned long long)k);
+            if (old == 0ull || old == k) break;
+        }
+        p = (p + 1) & mask;
+    }
+    w.slot_of[i] = (uint32_t)p;
+    atomicMax(&w.dd[p].last, (uint32_t)(i + 1));
+    if (t.policy == 2) {  // LFU: saturating sum of the increments
+        const uint64_t inc = scores ? scores[i] : 1ull;
+        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + p), (unsigned long long)inc);
+        if (old + inc < old) atomicOr(&w.dd[p].sat, 1u);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
+                                               const uint64_t* __restrict__ scores, uint64_t clock) {
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= n) return;
+    const int lane = glane<G>();
+    const uint32_t p = w.slot_of[i];
+    if (p == kNoSlot || w.dd[p].last != (uint32_t)(i + 1)) return;  // not the last occurrence
+    const uint64_t k = keys[i];
+    const KeyHash h = hash_key(t, k);
+    const bool two = h.b2 != h.b1;
+    LineSeg<G> s1, s2;
+    s1.load(t.dig + (size_t)h.b1 * kSlots, lane);
+    if (two) s2.load(t.dig + (size_t)h.b2 * kSlots, lane);  // an insert needs both occupancies
+    int slot = verify<G>(t, h.b1, s1.match(h.dg), k, lane);
+    uint32_t tgt = h.b1;
+    if (slot < 0 && two) {
+        slot = verify<G>(t, h.b2, s2.match(h.dg), k, lane);
+        tgt = h.b2;
+    }
+    uint64_t inc = 0;
+    if (t.policy == 2) inc = w.dd[p].sat ? ~0ull : w.inc[p];
+    uint64_t ns;
+    uint8_t islot;
+    if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
+        if (t.policy == 0) ns = scores[i];
+        else if (t.policy == 1) ns = clock;
+        else ns = sat_add(t.scores[(size_t)tgt * kSlots + slot], inc);
+        islot = (uint8_t)slot;
+    } else {  // INSERT: candidate choice (Alg. 3)
+        tgt = h.b1;
+        if (two) {
+            const int occ1 = kSlots - gsum_i<G>(__popc(s1.empty_mask()));
+            const int occ2 = kSlots - gsum_i<G>(__popc(s2.empty_mask()));
+            if (occ1 < kSlots || occ2 < kSlots) {  // phase D1: less occupied, b1 on a tie
+                if (occ2 < occ1) tgt = h.b2;
+            } else {  // phase D2: smaller minimum (score, key)
+                uint64_t m1s = t.bmin[2 * (size_t)h.b1], m1k = t.bmin[2 * (size_t)h.b1 + 1];
+                uint64_t m2s = t.bmin[2 * (size_t)h.b2], m2k = t.bmin[2 * (size_t)h.b2 + 1];
+                if (m1k == 0) bucket_min<G>(t, h.b1, lane, m1s, m1k);
+                if (m2k == 0) bucket_min<G>(t, h.b2, lane, m2s, m2k);
+                if (m2s < m1s || (m2s == m1s && m2k < m1k)) tgt = h.b2;
+            }
+        }
+        if (t.policy == 0) ns = scores[i];
+        else if (t.policy == 1) ns = clock;
+        else ns = inc;
+        islot = kInsertSlot;
+    }
+    if (lane == 0) {
+        const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
+        const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
+        if (r < w.cap) {
+            const size_t x = (size_t)tgt * w.cap + r;
+            w.ik[x] = k;
+            w.is[x] = ns;
+            w.iw[x] = wv;
+            w.islot[x] = islot;
+        } else {
+            const uint64_t ok = overflow_key(tgt, r);
+            uint64_t q = scratch_hash(ok, w.logP);
+            for (uint64_t probes = 0; probes < w.P; ++probes) {
+                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(w.okey + q), 0ull,
+                                                         (unsigned long long)ok);
+                if (old == 0ull) break;
+                q = (q + 1) & (w.P - 1);
+            }
+            w.ok[q] = k;
+            w.os[q] = ns;
+            w.ow[q] = wv;
+            w.oslot[q] = islot;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// fast apply: one 16-lane group per bucket with 1..16 operations
+__device__ __forceinline__ int nth_bit128(uint64_t lo, uint64_t hi, int r) {
+    const int c = __popcll(lo);
+    uint64_t x = lo;
+    int base = 0;
+    if (r >= c) {
+        r -= c;
+        x = hi;
+        base = 64;
+    }
+    for (int q = 0; q < r; ++q) x &= x - 1;
+    return base + __ffsll((unsigned long long)x) - 1;
+}
+
+__global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
+    __shared__ uint32_t s_nev[64];
+    __shared__ uint32_t s_off[64];
+    __shared__ unsigned long long s_base;
+    const int g = threadIdx.x / GA;
+    const int lane = threadIdx.x % GA;
+    const int gshift = (threadIdx.x & 63) & ~(GA - 1);
+    const uint64_t bb = (uint64_t)blockIdx.x * 64 + g;
+    const uint32_t b = (uint32_t)bb;
+    uint32_t m = 0;
+    if (bb < t.nbuckets) m = t.cnt[b];
+    if (m > (uint32_t)kFastMax) {
+        if (lane == 0) w.slow[atomicAdd(w.ctr + kCtrSlow, 1u)] = b;
+        m = 0;
+    }
+    const size_t eb = (size_t)b * kSlots;
+
+    // state carried over the block barrier
+    Entry e{0, 0, 0, kInsertSlot};
+    bool is_upd = false, is_ins = false, evicts = false;
+    int new_slot = -1, evi = 0;
+    uint64_t vkey = 0, vscore = 0;
+    uint32_t emask8 = 0, taken = 0, kloaded = 0, upd_bits = 0, ins_bits = 0;
+    uint64_t sc[SPL], kc[SPL];
+    bool full_after = false;
+    uint32_t nev = 0;
+
+    if (m > 0) {
+        const bool has = lane < (int)m;
+        if (has) e = fetch_entry(w, b, (uint32_t)lane);
+        is_upd = has && e.slot != kInsertSlot;
+        is_ins = has && e.slot == kInsertSlot;
+        const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
+        emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
+        const int occ = kSlots - gsum_i<GA>(__popc(emask8));
+        const int nfree = kSlots - occ;
+        upd_bits = (uint32_t)((__ballot(is_upd) >> gshift) & 0xFFFFu);
+        ins_bits = (uint32_t)((__ballot(is_ins) >> gshift) & 0xFFFFu);
+        const int ni = __popc(ins_bits);
+        full_after = occ + ni >= kSlots;
+
+        // rank among the inserts: (score desc, key asc)
+        int rank = 0;
+        for (int x = 0; x < (int)m; ++x) {
+            const uint64_t sx = __shfl(e.score, x, GA);
+            const uint64_t kx = __shfl(e.key, x, GA);
+            rank += (int)(((ins_bits >> x) & 1u) && (sx > e.score || (sx == e.score && kx < e.key)));
+        }
+        // free slots of the bucket as a 128-bit mask
+        uint64_t elo = 0, ehi = 0;
+        if (ni > 0) {
+#pragma unroll
+            for (int q = 0; q < GA; ++q) {
+                const uint64_t mq = (uint64_t)__shfl((int)emask8, q, GA) & 0xFFull;
+                if (q < 8) elo |= mq << (8 * q);
+                else ehi |= mq << (8 * (q - 8));
+            }
+        }
+        if (is_ins && rank < nfree) new_slot = nth_bit128(elo, ehi, rank);
+
+        if (full_after) {  // scores of the bucket, with this call's updates applied
+            const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
+#pragma unroll
+            for (int q = 0; q < SPL / 2; ++q) {
+                const ulonglong2 v = sp[q];
+                sc[2 * q] = v.x;
+                sc[2 * q + 1] = v.y;
+            }
+            for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
+                const int x = __ffs(ub) - 1;
+                const int us = __shfl((int)e.slot, x, GA);
+                const uint64_t usc = __shfl(e.score, x, GA);
+#pragma unroll
+                for (int q = 0; q < SPL; ++q)
+                    if ((us >> 3) == lane && (us & 7) == q) sc[q] = usc;
+            }
+        }
+        // victims for the inserts ranked nfree, nfree+1, ... (strict admission, Alg. 2)
+        const int want = ni - nfree;
+        for (int v = 0; v < want; ++v) {
+            const uint32_t rb = (uint32_t)((__ballot(is_ins && rank == nfree + v) >> gshift) & 0xFFFFu);
+            const int rl = __ffs(rb) - 1;
+            const uint64_t s_in = __shfl(e.score, rl, GA);
+            uint64_t lm = ~0ull;
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (!((emask8 | taken) >> q & 1u)) lm = sc[q] < lm ? sc[q] : lm;
+            const uint64_t gm = gmin_u64<GA>(lm);
+            if (!(s_in > gm)) break;  // rejected, and so is every later insert
+            uint64_t lk = ~0ull;
+            int lslot = -1;
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                if (!((emask8 | taken) >> q & 1u) && sc[q] == gm) {
+                    if (!(kloaded >> q & 1u)) {
+                        kc[q] = t.keys[eb + lane * SPL + q];
+                        kloaded |= 1u << q;
+                    }
+                    if (kc[q] < lk) {
+                        lk = kc[q];
+                        lslot = lane * SPL + q;
+                    }
+                }
+            }
+            const uint64_t gk = gmin_u64<GA>(lk);
+            const uint32_t ob = (uint32_t)((__ballot(lslot >= 0 && lk == gk) >> gshift) & 0xFFFFu);
+            const int ol = __ffs(ob) - 1;
+            const int vsl = __shfl(lslot, ol, GA);
+            if (lane == ol) taken |= 1u << (vsl & 7);
+            if (lane == rl) {
+                new_slot = vsl;
+                vkey = gk;
+                vscore = gm;
+                evi = v;
+                evicts = true;
+            }
+            ++nev;
+        }
+    }
+
+    // eviction output positions: one atomic per block
+    if (ev.count) {
+        if (lane == 0) s_nev[g] = nev;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int q = 0; q < 64; ++q) {
+                s_off[q] = tot;
+                tot += s_nev[q];
+            }
+            s_base = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(ev.count), (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+    }
+    if (m == 0) return;
+    const uint64_t ev_base = ev.count ? s_base + s_off[g] : 0ull;
+
+    // statuses and evicted (key, score)
+    if (is_upd) w.sstat[e.w >> 32] = 1;  // UPDATED
+    if (is_ins) w.sstat[e.w >> 32] = new_slot < 0 ? 4 : (evicts ? 3 : 2);
+    if (evicts && ev.keys) {
+        ev.keys[ev_base + evi] = vkey;
+        ev.scores[ev_base + evi] = vscore;
+    }
+    // slot metadata, by the owning lane: updates first, then inserts
+    for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
+        const int x = __ffs(ub) - 1;
+        const int us = __shfl((int)e.slot, x, GA);
+        const uint64_t usc = __shfl(e.score, x, GA);
+        if ((us >> 3) == lane) t.scores[eb + us] = usc;
+    }
+    for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
+        const int x = __ffs(ib) - 1;
+        const int ns = __shfl(new_slot, x, GA);
+        if (ns < 0) continue;
+        const uint64_t nk = __shfl(e.key, x, GA);
+        const uint64_t nsc = __shfl(e.score, x, GA);
+        if ((ns >> 3) == lane) {
+            t.keys[eb + ns] = nk;
+            t.scores[eb + ns] = nsc;
+            t.dig[eb + ns] = (uint8_t)hash_key(t, nk).dg;
+            if (full_after) {
+#pragma unroll
+                for (int q = 0; q < SPL; ++q)
+                    if ((ns & 7) == q) {
+                        sc[q] = nsc;
+                        kc[q] = nk;
+                    }
+                kloaded |= 1u << (ns & 7);
+                emask8 &= ~(1u << (ns & 7));
+            }
+        }
+    }
+    // rows: chunk c of every row by lane c mod 16; updates before evictions
+    const uint32_t chunks = t.dim >> 2;
+    for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
+        const int x = __ffs(ub) - 1;
+        const int us = __shfl((int)e.slot, x, GA);
+        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
+        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+        for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+    }
+    for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
+        const int x = __ffs(ib) - 1;
+        const int ns = __shfl(new_slot, x, GA);
+        if (ns < 0) continue;
+        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+        const bool xe = __shfl((int)evicts, x, GA) != 0;
+        const int xi = __shfl(evi, x, GA);
+        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + ns) * t.dim);
+        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+        if (xe && ev.vals) {
+            uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) {
+                const uint4 old = dst[c];
+                out[c] = old;
+                dst[c] = src[c];
+            }
+        } else {
+            for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+        }
+    }
+    // cached minimum of a full bucket (exact; every slot is occupied now)
+    if (full_after) {
+        uint64_t lm = ~0ull;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) lm = sc[q] < lm ? sc[q] : lm;
+        const uint64_t gm = gmin_u64<GA>(lm);
+        uint64_t lk = ~0ull;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            if (sc[q] == gm) {
+                if (!(kloaded >> q & 1u)) kc[q] = t.keys[eb + lane * SPL + q];
+                lk = kc[q] < lk ? kc[q] : lk;
+            }
+        }
+        const uint64_t gk = gmin_u64<GA>(lk);
+        if (lane == 0) {
+            t.bmin[2 * (size_t)b] = gm;
+            t.bmin[2 * (size_t)b + 1] = gk;
+        }
+    }
+    if (lane == 0) t.cnt[b] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// slow apply: one wave per bucket with more than 16 operations
+__global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
+    __shared__ uint64_t cs[192], ck[192], cw[192];  // insert candidates: score, key, w
+    __shared__ uint64_t ns_[128], nk_[128], nw_[128];
+    __shared__ uint64_t S_[128], K_[128];           // residents by slot (updates applied)
+    __shared__ uint64_t rs[128], rk[128];           // smallest residents in (score, key) order
+    __shared__ uint8_t rslot[128], elist[128], dslot[128], uflag[128], nflag[128];
+    __shared__ uint64_t newk[128], news[128];
+    __shared__ unsigned long long ev_base_s;
+
+    const int lane = threadIdx.x;
+    const uint32_t nslow = w.ctr[kCtrSlow];
+    const uint32_t chunks = t.dim >> 2;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (uint32_t si = blockIdx.x; si < nslow; si += gridDim.x) {
+        const uint32_t b = w.slow[si];
+        const uint32_t m = t.cnt[b];
+        const size_t eb = (size_t)b * kSlots;
+
+        // residents
+        const bool o0 = t.dig[eb + lane] != 0;
+        const bool o1 = t.dig[eb + lane + 64] != 0;
+        S_[lane] = o0 ? t.scores[eb + lane] : ~0ull;
+        K_[lane] = o0 ? t.keys[eb + lane] : ~0ull;
+        S_[lane + 64] = o1 ? t.scores[eb + lane + 64] : ~0ull;
+        K_[lane + 64] = o1 ? t.keys[eb + lane + 64] : ~0ull;
+        uflag[lane] = uflag[lane + 64] = 0;
+        nflag[lane] = nflag[lane + 64] = 0;
+        const uint64_t bal0 = __ballot(o0), bal1 = __ballot(o1);
+        const int occ = __popcll(bal0) + __popcll(bal1);
+        const int nfree = kSlots - occ;
+        if (!o0) elist[__popcll(~bal0 & below)] = (uint8_t)lane;
+        if (!o1) elist[__popcll(~bal0) + __popcll(~bal1 & below)] = (uint8_t)(lane + 64);
+        __syncthreads();
+
+        // stream the operations: updates applied at once, inserts reduced to the best 128
+        int nbest = 0;
+        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+            const bool has = c0 + lane < m;
+            Entry e{0, 0, 0, kInsertSlot};
+            if (has) e = fetch_entry(w, b, c0 + lane);
+            const bool upd = has && e.slot != kInsertSlot;
+            const bool ins = has && e.slot == kInsertSlot;
+            if (upd) {
+                S_[e.slot] = e.score;
+                uflag[e.slot] = 1;
+                w.sstat[e.w >> 32] = 1;  // UPDATED
+            }
+            for (uint64_t ub = __ballot(upd); ub; ub &= ub - 1) {
+                const int x = __ffsll((unsigned long long)ub) - 1;
+                const int us = __shfl((int)e.slot, x);
+                const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x);
+                uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
+                const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+                for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
+            }
+            const uint64_t ib = __ballot(ins);
+            const int cn = __popcll(ib);
+            if (ins) {
+                const int at = nbest + __popcll(ib & below);
+                cs[at] = e.score;
+                ck[at] = e.key;
+                cw[at] = e.w;
+            }
+            __syncthreads();
+            const int tot = nbest + cn;
+            int r[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int j = lane + 64 * q;
+                r[q] = -1;
+                if (j < tot) {
+                    const uint64_t s = cs[j], k = ck[j];
+                    int rr = 0;
+                    for (int x = 0; x < tot; ++x) {
+                        const uint64_t sx = cs[x];
+                        rr += (sx > s) || (sx == s && ck[x] < k);
+                    }
+                    r[q] = rr;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int j = lane + 64 * q;
+                if (j < tot) {
+                    if (r[q] < 128) {
+                        ns_[r[q]] = cs[j];
+                        nk_[r[q]] = ck[j];
+                        nw_[r[q]] = cw[j];
+                    } else {
+                        w.sstat[cw[j] >> 32] = 4;  // REJECTED: 128 better inserts target this bucket
+                    }
+                }
+            }
+            __syncthreads();
+            nbest = min(tot, 128);
+            for (int j = lane; j < nbest; j += 64) {
+                cs[j] = ns_[j];
+                ck[j] = nk_[j];
+                cw[j] = nw_[j];
+            }
+            __syncthreads();
+        }
+
+        // the smallest residents, in (score asc, key asc) order
+        const int need = nbest - nfree;
+        if (need > 0) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int sl = lane + 64 * q;
+                if (!(q ? o1 : o0)) continue;
+                const uint64_t s = S_[sl], k = K_[sl];
+                int rr = 0;
+                for (int x = 0; x < kSlots; ++x) {
+                    const uint64_t sx = S_[x];
+                    rr += (sx < s) || (sx == s && K_[x] < k);  // free slots sort last (~0, ~0)
+                }
+                if (rr < need) {
+                    rs[rr] = s;
+                    rk[rr] = k;
+                    rslot[rr] = (uint8_t)sl;
+                }
+            }
+        }
+        __syncthreads();
+
+        // decisions: insert j takes free slot j, or competes with the (j-nfree)-th smallest resident
+        bool adm[2];
+        uint8_t st[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int j = lane + 64 * q;
+            adm[q] = false;
+            st[q] = 0;
+            if (j < nbest) {
+                if (j < nfree) {
+                    adm[q] = true;
+                    st[q] = 2;  // INSERTED
+                    dslot[j] = elist[j];
+                } else {
+                    const int v = j - nfree;
+                    if (v < occ && cs[j] > rs[v]) {
+                        adm[q] = true;
+                        st[q] = 3;  // INSERTED_EVICT
+                        dslot[j] = rslot[v];
+                    } else {
+                        st[q] = 4;  // REJECTED
+                    }
+                }
+            }
+        }
+        const int nadm = __popcll(__ballot(adm[0])) + __popcll(__ballot(adm[1]));
+        const int nev = nadm > nfree ? nadm - nfree : 0;
+        if (lane == 0)
+            ev_base_s = (ev.count && nev) ? atomicAdd(reinterpret_cast<unsigned long long*>(ev.count), (unsigned long long)nev)
+                                          : 0ull;
+        __syncthreads();
+        const uint64_t ev_base = ev_base_s;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int j = lane + 64 * q;
+            if (j >= nbest) continue;
+            w.sstat[cw[j] >> 32] = st[q];
+            if (!adm[q]) continue;
+            if (st[q] == 3 && ev.keys) {
+                const uint64_t x = ev_base + (uint64_t)(j - nfree);
+                ev.keys[x] = rk[j - nfree];
+                ev.scores[x] = rs[j - nfree];
+            }
+            nflag[dslot[j]] = 1;
+            newk[dslot[j]] = ck[j];
+            news[dslot[j]] = cs[j];
+        }
+        // rows of admitted inserts: chunk c by lane c mod 64; victims copied out first
+        for (int j = 0; j < nadm; ++j) {
+            uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + dslot[j]) * t.dim);
+            const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)(uint32_t)cw[j] * t.dim);
+            if (j >= nfree && ev.vals) {
+                uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + (uint64_t)(j - nfree)) * t.dim);
+                for (uint32_t c = lane; c < chunks; c += 64) {
+                    const uint4 old = dst[c];
+                    out[c] = old;
+                    dst[c] = src[c];
+                }
+            } else {
+                for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
+            }
+        }
+        __syncthreads();
+        // slot metadata by the owning lane; the minimum of the full bucket
+        uint64_t lm = ~0ull, lk = ~0ull;
+        const bool full = nadm >= nfree;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int sl = lane + 64 * q;
+            if (nflag[sl]) {
+                t.keys[eb + sl] = newk[sl];
+                t.scores[eb + sl] = news[sl];
+                t.dig[eb + sl] = (uint8_t)hash_key(t, newk[sl]).dg;
+                S_[sl] = news[sl];
+                K_[sl] = newk[sl];
+            } else if (uflag[sl]) {
+                t.scores[eb + sl] = S_[sl];
+            }
+            if (S_[sl] < lm || (S_[sl] == lm && K_[sl] < lk)) {
+                lm = S_[sl];
+                lk = K_[sl];
+            }
+        }
+        if (full) {
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint64_t xm = __shfl_xor(lm, o), xk = __shfl_xor(lk, o);
+                if (xm < lm || (xm == lm && xk < lk)) {
+                    lm = xm;
+                    lk = xk;
+                }
+            }
+            if (lane == 0) {
+                t.bmin[2 * (size_t)b] = lm;
+                t.bmin[2 * (size_t)b + 1] = lk;
+            }
+        }
+        if (lane == 0) t.cnt[b] = 0;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t* __restrict__ status) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = w.slot_of[i];
+    status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
+}
+
+template <int G>
+static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
+                         uint64_t clock, hipStream_t s) {
+    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, clock);
+}
+
+hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
+                         const uint64_t* scores, uint8_t* status, const EvictOut& ev, uint64_t clock, size_t zero_bytes,
+                         int group, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipError_t e = launch_fill_zero(w.dd, zero_bytes, s);
+    if (e != hipSuccess) return e;
+    k_dedupe<<<blocks_for(n, 256), 256, 0, s>>>(t, w, n, keys, scores, ev.count);
+    switch (group) {
+        case 4: launch_route<4>(t, w, n, keys, scores, clock, s); break;
+        case 16: launch_route<16>(t, w, n, keys, scores, clock, s); break;
+        default: launch_route<8>(t, w, n, keys, scores, clock, s); break;
+    }
+    k_apply_fast<<<(unsigned)((t.nbuckets + 63) / 64), 1024, 0, s>>>(t, w, vals, ev);
+    uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
+    if (slow_blocks > 2048) slow_blocks = 2048;
+    k_apply_slow<<<(unsigned)slow_blocks, 64, 0, s>>>(t, w, vals, ev);
+    if (status) k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status);
+    return hipGetLastError();
+}
+
+}  // namespace cskv
