@@ -87,8 +87,9 @@ enum { CSKV_OP_FIND = 0, CSKV_OP_INSERT_OR_ASSIGN = 1, CSKV_OP_INSERT_AND_EVICT 
 /*
  * Bytes of device storage a table needs (Sec. 3.2 bucket layout, Sec. 3.6 value store):
  * per bucket a 128-B digest line, 128 keys, 128 scores, 128 value rows, plus 20 B of per-bucket
- * bookkeeping (an operation counter and the cached minimum entry of a full bucket).  capacity must be 128 * B with B a power of two, 1 <= B <= 2^24; bucket_size
- * must be 128.  Returns 0 if the arguments are invalid.
+ * bookkeeping (an operation counter and the cached minimum entry of a full bucket).
+ * capacity must be 128 * B with B a power of two, 1 <= B <= 2^24; bucket_size must be 128.
+ * Returns 0 if the arguments are invalid.
  */
 size_t cskv_table_bytes(uint64_t capacity, uint32_t bucket_size, uint32_t dim);
 
