@@ -77,6 +77,42 @@ def clone(src: cskv.Table) -> cskv.Table:
     return dst
 
 
+def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3):
+    """Pick find group/prefetch and route group by HIP-event timing on sample batches."""
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return min(ts)
+
+    best = None
+    for g in (4, 8, 16):
+        for pre in (0, 1):
+            t.set_tuning(find_group=g, find_prefetch_b2=pre)
+            ms = timed(lambda: (t.find(q100, values_out=outs, found_out=found, want_scores=False),
+                                t.find(q50, values_out=outs, found_out=found, want_scores=False)))
+            log(f"autotune find group {g} prefetch {pre}: {ms:.3f} ms")
+            if best is None or ms < best[0]:
+                best = (ms, g, pre)
+    tuning = {"find_group": best[1], "find_prefetch_b2": best[2]}
+    t.set_tuning(**tuning)
+    best_r = None
+    for g in (8, 16):
+        t.set_tuning(route_group=g)
+        ms = timed(lambda: (t.insert_or_assign(fresh, rows, status_out=status), t.erase(fresh, erased_out=erased)))
+        log(f"autotune route group {g}: {ms:.3f} ms")
+        if best_r is None or ms < best_r[0]:
+            best_r = (ms, g)
+    tuning["route_group"] = best_r[1]
+    return tuning
+
+
 def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
     """Sequential C oracle (one thread) on a sample: a 2^22-slot dual LRU table filled to each
     load factor (untimed), then the step's three ops on 2^18-key batches, timed."""
@@ -170,6 +206,13 @@ def main():
         lv.t.workspace(cskv.OP_ERASE, batch)
     torch.cuda.synchronize()
 
+    # autotune launch shapes (results do not depend on them) on the first table
+    tuning = autotune(levels[0].t, q100[0], q50[0], gen_keys(700, batch, 0, device=dev), rows, outs, found, status,
+                      erased)
+    for lv in levels:
+        lv.t.set_tuning(**tuning)
+    log(f"tuning: {tuning}")
+
     ev = {}
 
     def rec(name):
@@ -245,7 +288,8 @@ def main():
         "per_op": per_op,
         "latency_ms": {k: {"p50": round(float(np.percentile(v, 50)), 4), "p99": round(float(np.percentile(v, 99)), 4)}
                        for k, v in lat.items() if v},
-        "roofline": {"bound": "hbm", "kernel": "k_find<8>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "tuning": tuning,
+        "roofline": {"bound": "hbm", "kernel": f"k_find<{tuning['find_group']},{bool(tuning['find_prefetch_b2'])}>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     if not args.no_cpu_baseline:

@@ -168,6 +168,19 @@ int cskv_size(cskv_table* table, uint64_t* d_size, void* stream);
 int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t* d_keys,
                 float* d_values, uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count, void* stream);
 
+/*
+ * Launch-shape tuning (results never depend on it; the autotuner sets these):
+ *  CSKV_TUNE_FIND_GROUP        lanes per key of the find and erase probes: 4, 8 (default) or 16
+ *  CSKV_TUNE_ROUTE_GROUP       lanes per key of the upsert routing kernel: 4, 8 (default) or 16
+ *  CSKV_TUNE_FIND_PREFETCH_B2  1 = find loads both candidates' digest lines at once, 0 = b2 only
+ *                              after a miss in b1 (default)
+ * cskv_set_tuning returns CSKV_EINVAL for an unknown parameter or value; cskv_get_tuning returns
+ * the current value, or -1.
+ */
+enum { CSKV_TUNE_FIND_GROUP = 1, CSKV_TUNE_ROUTE_GROUP = 2, CSKV_TUNE_FIND_PREFETCH_B2 = 3 };
+int cskv_set_tuning(cskv_table* table, int param, int value);
+int cskv_get_tuning(const cskv_table* table, int param);
+
 /* LRU logical clock (number of non-empty upsert calls so far, plus any value set below). */
 uint64_t cskv_clock(const cskv_table* table);
 int cskv_set_clock(cskv_table* table, uint64_t clock);

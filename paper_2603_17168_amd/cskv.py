@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcskv.so")
 MODE = {"single": 1, "dual": 2}
 POLICY = {"custom": 0, "lru": 1, "lfu": 2}
 OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE = 0, 1, 2, 3
+TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
 
 _lib = None
@@ -52,6 +53,8 @@ def lib():
         "cskv_erase": (I, [P, U64, P, P, P, SZ, P]),
         "cskv_size": (I, [P, P, P]),
         "cskv_export": (I, [P, U64, U64, P, P, P, P, P, P]),
+        "cskv_set_tuning": (I, [P, I, I]),
+        "cskv_get_tuning": (I, [P, I]),
         "cskv_clock": (U64, [P]),
         "cskv_set_clock": (I, [P, U64]),
         "cskv_num_buckets": (U64, [P]),
@@ -145,6 +148,14 @@ class Table:
     @clock.setter
     def clock(self, c: int):
         _check(lib().cskv_set_clock(self._h, c), "cskv_set_clock")
+
+    def set_tuning(self, **kw):
+        """Launch-shape knobs (find_group, route_group, find_prefetch_b2); results never change."""
+        for k, v in kw.items():
+            _check(lib().cskv_set_tuning(self._h, TUNE[k], int(v)), f"cskv_set_tuning({k}={v})")
+
+    def get_tuning(self) -> dict:
+        return {k: int(lib().cskv_get_tuning(self._h, v)) for k, v in TUNE.items()}
 
     def clear(self):
         with torch.cuda.device(self.device):

@@ -13,7 +13,9 @@ struct cskv_table {
     uint64_t clock;
     int mode;
     int policy;
-    int group;  // lanes per key for probe kernels
+    int group;        // lanes per key of the find / erase probe kernels
+    int route_group;  // lanes per key of the upsert route kernel
+    int prefetch_b2;  // find loads both candidate digest lines at once
 };
 
 namespace cskv {
@@ -62,17 +64,12 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.off_ctr = o;     o = align256(o + 64 * 4);
     L.off_zero_end = o;
     L.off_inc = o;     o = align256(o + P * 8);
+    L.off_sat = o;     o = align256(o + P * 4);
     L.off_zero_end_lfu = o;
     L.off_sstat = o;   o = align256(o + P);
     L.off_slot_of = o; o = align256(o + n * 4);
-    L.off_ik = o;      o = align256(o + nl * 8);
-    L.off_is = o;      o = align256(o + nl * 8);
-    L.off_iw = o;      o = align256(o + nl * 8);
-    L.off_islot = o;   o = align256(o + nl);
-    L.off_ok = o;      o = align256(o + P * 8);
-    L.off_os = o;      o = align256(o + P * 8);
-    L.off_ow = o;      o = align256(o + P * 8);
-    L.off_oslot = o;   o = align256(o + P);
+    L.off_il = o;      o = align256(o + nl * sizeof(OpEntry));
+    L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
     L.total = o;
     return L;
@@ -139,6 +136,8 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->mode = mode;
     t->policy = score_policy;
     t->group = 8;
+    t->route_group = 8;
+    t->prefetch_b2 = 0;
     const int rc = hip_rc(launch_clear_table(t->view, as_stream(stream)));
     if (rc != CSKV_OK) {
         delete t;
@@ -179,7 +178,7 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
     if (!aligned(d_keys, 8) || !aligned(d_values_out, 16) || (d_scores_out && !aligned(d_scores_out, 8)))
         return CSKV_EINVAL;
     return hip_rc(launch_find(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
-                              as_stream(stream)));
+                              table->prefetch_b2, as_stream(stream)));
 }
 
 static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
@@ -199,16 +198,11 @@ static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, 
     w.okey = reinterpret_cast<uint64_t*>(b + L.off_okey);
     w.ctr = reinterpret_cast<uint32_t*>(b + L.off_ctr);
     w.inc = reinterpret_cast<uint64_t*>(b + L.off_inc);
+    w.sat = reinterpret_cast<uint32_t*>(b + L.off_sat);
     w.sstat = b + L.off_sstat;
     w.slot_of = reinterpret_cast<uint32_t*>(b + L.off_slot_of);
-    w.ik = reinterpret_cast<uint64_t*>(b + L.off_ik);
-    w.is = reinterpret_cast<uint64_t*>(b + L.off_is);
-    w.iw = reinterpret_cast<uint64_t*>(b + L.off_iw);
-    w.islot = b + L.off_islot;
-    w.ok = reinterpret_cast<uint64_t*>(b + L.off_ok);
-    w.os = reinterpret_cast<uint64_t*>(b + L.off_os);
-    w.ow = reinterpret_cast<uint64_t*>(b + L.off_ow);
-    w.oslot = b + L.off_oslot;
+    w.il = reinterpret_cast<OpEntry*>(b + L.off_il);
+    w.ol = reinterpret_cast<OpEntry*>(b + L.off_ol);
     w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);
     w.P = L.P;
     w.logP = L.logP;
@@ -217,7 +211,7 @@ static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, 
     uint64_t clock = table->clock;
     if (table->policy == CSKV_SCORE_LRU) clock += 1;
     const int rc = hip_rc(launch_upsert(table->view, w, n, d_keys, d_values, d_scores, d_status, ev, clock, zero_bytes,
-                                        table->group, as_stream(stream)));
+                                        table->route_group, as_stream(stream)));
     if (rc == CSKV_OK) table->clock = clock;
     return rc;
 }
@@ -265,6 +259,35 @@ int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, u
         return CSKV_EINVAL;
     return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
                                 as_stream(stream)));
+}
+
+int cskv_set_tuning(cskv_table* table, int param, int value) {
+    if (!table) return CSKV_EINVAL;
+    switch (param) {
+        case CSKV_TUNE_FIND_GROUP:
+            if (value != 4 && value != 8 && value != 16) return CSKV_EINVAL;
+            table->group = value;
+            return CSKV_OK;
+        case CSKV_TUNE_ROUTE_GROUP:
+            if (value != 4 && value != 8 && value != 16) return CSKV_EINVAL;
+            table->route_group = value;
+            return CSKV_OK;
+        case CSKV_TUNE_FIND_PREFETCH_B2:
+            if (value != 0 && value != 1) return CSKV_EINVAL;
+            table->prefetch_b2 = value;
+            return CSKV_OK;
+        default: return CSKV_EINVAL;
+    }
+}
+
+int cskv_get_tuning(const cskv_table* table, int param) {
+    if (!table) return -1;
+    switch (param) {
+        case CSKV_TUNE_FIND_GROUP: return table->group;
+        case CSKV_TUNE_ROUTE_GROUP: return table->route_group;
+        case CSKV_TUNE_FIND_PREFETCH_B2: return table->prefetch_b2;
+        default: return -1;
+    }
 }
 
 uint64_t cskv_clock(const cskv_table* table) { return table ? table->clock : 0; }

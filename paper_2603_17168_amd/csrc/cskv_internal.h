@@ -10,12 +10,13 @@
 //     bmin   u64[B][2]            (score, key) of a full bucket's minimum entry; key 0 = not known
 //
 //   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity):
-//     zeroed on entry: dd {key u64, last u32, sat u32}[P], okey u64[P], ctr u32[64], inc u64[P] (LFU)
+//     zeroed on entry: dd {key u64, last u32, claim u32}[P], okey u64[P], ctr u32[64],
+//                      and for LFU inc u64[P], sat u32[P]
 //     sstat u8[P]                      status of each distinct key's operation
 //     slot_of u32[n]                   dedupe slot of input i (or kNoSlot)
-//     ik, is, iw u64[B*C], islot u8[B*C]   per-bucket operation lists: key, new score,
+//     il OpEntry[B*C]                  per-bucket operation lists: key, new score,
 //                                      (dedupe slot << 32 | input position), slot (0xFF = insert)
-//     ok, os, ow u64[P], oslot u8[P]   the same for list positions >= C, hashed on (bucket, position)
+//     ol OpEntry[P]                    list positions >= C, hashed on (bucket, position) via okey
 //     slow u32[min(n, B)]              buckets with more operations than the fast path takes
 #pragma once
 
@@ -48,8 +49,15 @@ struct TableView {
 
 struct DedupeEntry {
     uint64_t key;
-    uint32_t last;  // index of the last occurrence + 1
-    uint32_t sat;   // LFU: the increment sum overflowed
+    uint32_t last;   // largest index + 1 among the occurrences that found the key already claimed
+    uint32_t claim;  // index + 1 of the occurrence that claimed the entry
+};
+
+struct OpEntry {
+    uint64_t key;
+    uint64_t score;
+    uint64_t w;     // dedupe slot << 32 | input position
+    uint64_t slot;  // table slot of an update, kInsertSlot for an insert
 };
 
 struct UpsertWs {
@@ -57,12 +65,11 @@ struct UpsertWs {
     uint64_t* okey;
     uint32_t* ctr;
     uint64_t* inc;
+    uint32_t* sat;
     uint8_t* sstat;
     uint32_t* slot_of;
-    uint64_t *ik, *is, *iw;
-    uint8_t* islot;
-    uint64_t *ok, *os, *ow;
-    uint8_t* oslot;
+    OpEntry* il;
+    OpEntry* ol;
     uint32_t* slow;
     uint64_t P;
     int logP;
@@ -81,9 +88,8 @@ struct StorageLayout {
 };
 
 struct UpsertLayout {
-    size_t off_dd, off_okey, off_ctr, off_inc, off_zero_end, off_zero_end_lfu;
-    size_t off_sstat, off_slot_of, off_ik, off_is, off_iw, off_islot, off_ok, off_os, off_ow, off_oslot, off_slow,
-        total;
+    size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_zero_end, off_zero_end_lfu;
+    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, total;
     uint64_t P;
     int logP;
     uint32_t cap;
@@ -97,7 +103,7 @@ size_t erase_ws_bytes(uint64_t n);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_clear_table(const TableView& t, hipStream_t s);
 hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
-                       uint64_t* scores_out, int group, hipStream_t s);
+                       uint64_t* scores_out, int group, int prefetch_b2, hipStream_t s);
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
                          const float* vals, const uint64_t* scores, uint8_t* status, const EvictOut& ev,
                          uint64_t clock, size_t zero_bytes, int group, hipStream_t s);

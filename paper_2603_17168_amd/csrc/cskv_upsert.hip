@@ -4,12 +4,13 @@
 //
 // One call is a fixed sequence on one stream:
 //   zero     one fill of the call's scratch (dedupe set, overflow keys, counters)
-//   dedupe   one set entry per distinct key: last occurrence (atomicMax), LFU increment sum
+//   dedupe   one set entry per distinct key (one CAS per distinct key; atomicMax only for
+//            repeats): last occurrence, LFU increment sum
 //   route    G lanes per distinct key, against the table as it was before the call: update slot
 //            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
 //            smaller cached bucket minimum (score, key)); the operation is appended to the
 //            target bucket's list (rank from an atomic count per bucket)
-//   apply    16 lanes per bucket (8 slots each), 64 buckets per 1024-thread block: updates,
+//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block: updates,
 //            then inserts ranked by (score desc, key asc): the first ones take free slots, the
 //            rest compete with the smallest residents by (score, key) - strict admission;
 //            victims are copied out, slots written, the bucket minimum cached when full
@@ -40,24 +41,29 @@ struct Entry {
 };
 
 // the r-th operation routed to bucket b
-__device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
+__device__ __forceinline__ Entry load_entry(const OpEntry* p) {
+    const ulonglong2* q = reinterpret_cast<const ulonglong2*>(p);
+    const ulonglong2 a = q[0], c = q[1];
     Entry e;
-    if (r < w.cap) {
-        const size_t x = (size_t)b * w.cap + r;
-        e.key = w.ik[x];
-        e.score = w.is[x];
-        e.w = w.iw[x];
-        e.slot = w.islot[x];
-        return e;
-    }
+    e.key = a.x;
+    e.score = a.y;
+    e.w = c.x;
+    e.slot = (uint8_t)c.y;
+    return e;
+}
+
+__device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t score, uint64_t w, uint8_t slot) {
+    ulonglong2* q = reinterpret_cast<ulonglong2*>(p);
+    q[0] = make_ulonglong2(key, score);
+    q[1] = make_ulonglong2(w, (unsigned long long)slot);
+}
+
+__device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
+    if (r < w.cap) return load_entry(w.il + (size_t)b * w.cap + r);
     const uint64_t ok = overflow_key(b, r);
     uint64_t q = scratch_hash(ok, w.logP);
     for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
-    e.key = w.ok[q];
-    e.score = w.os[q];
-    e.w = w.ow[q];
-    e.slot = w.oslot[q];
-    return e;
+    return load_entry(w.ol + q);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -71,24 +77,28 @@ __global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_
         w.slot_of[i] = kNoSlot;
         return;
     }
+    // one atomic per distinct key: the occurrence that claims the entry records its index with a
+    // plain store; later occurrences of the key raise `last` with atomicMax
     const uint64_t mask = w.P - 1;
     uint64_t p = scratch_hash(k, w.logP);
     for (uint64_t probes = 0; probes < w.P; ++probes) {
-        const uint64_t cur = w.dd[p].key;
-        if (cur == k) break;
-        if (cur == 0) {
-            const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[p].key), 0ull,
-                                                     (unsigned long long)k);
-            if (old == 0ull || old == k) break;
+        const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[p].key), 0ull,
+                                                 (unsigned long long)k);
+        if (old == 0ull) {
+            w.dd[p].claim = (uint32_t)(i + 1);
+            break;
+        }
+        if (old == k) {
+            atomicMax(&w.dd[p].last, (uint32_t)(i + 1));
+            break;
         }
         p = (p + 1) & mask;
     }
     w.slot_of[i] = (uint32_t)p;
-    atomicMax(&w.dd[p].last, (uint32_t)(i + 1));
     if (t.policy == 2) {  // LFU: saturating sum of the increments
         const uint64_t inc = scores ? scores[i] : 1ull;
         const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + p), (unsigned long long)inc);
-        if (old + inc < old) atomicOr(&w.dd[p].sat, 1u);
+        if (old + inc < old) atomicOr(w.sat + p, 1u);
     }
 }
 
@@ -100,7 +110,9 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     if (i >= n) return;
     const int lane = glane<G>();
     const uint32_t p = w.slot_of[i];
-    if (p == kNoSlot || w.dd[p].last != (uint32_t)(i + 1)) return;  // not the last occurrence
+    if (p == kNoSlot) return;
+    const DedupeEntry de = w.dd[p];
+    if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
     const uint64_t k = keys[i];
     const KeyHash h = hash_key(t, k);
     const bool two = h.b2 != h.b1;
@@ -114,7 +126,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         tgt = h.b2;
     }
     uint64_t inc = 0;
-    if (t.policy == 2) inc = w.dd[p].sat ? ~0ull : w.inc[p];
+    if (t.policy == 2) inc = w.sat[p] ? ~0ull : w.inc[p];
     uint64_t ns;
     uint8_t islot;
     if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
@@ -146,11 +158,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         if (r < w.cap) {
-            const size_t x = (size_t)tgt * w.cap + r;
-            w.ik[x] = k;
-            w.is[x] = ns;
-            w.iw[x] = wv;
-            w.islot[x] = islot;
+            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot);
         } else {
             const uint64_t ok = overflow_key(tgt, r);
             uint64_t q = scratch_hash(ok, w.logP);
@@ -160,10 +168,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
                 if (old == 0ull) break;
                 q = (q + 1) & (w.P - 1);
             }
-            w.ok[q] = k;
-            w.os[q] = ns;
-            w.ow[q] = wv;
-            w.oslot[q] = islot;
+            store_entry(w.ol + q, k, ns, wv, islot);
         }
     }
 }
@@ -183,14 +188,16 @@ __device__ __forceinline__ int nth_bit128(uint64_t lo, uint64_t hi, int r) {
     return base + __ffsll((unsigned long long)x) - 1;
 }
 
-__global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
-    __shared__ uint32_t s_nev[64];
-    __shared__ uint32_t s_off[64];
+constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
+
+__global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
+    __shared__ uint32_t s_nev[kApplyGroups];
+    __shared__ uint32_t s_off[kApplyGroups];
     __shared__ unsigned long long s_base;
     const int g = threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     const int gshift = (threadIdx.x & 63) & ~(GA - 1);
-    const uint64_t bb = (uint64_t)blockIdx.x * 64 + g;
+    const uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
     const uint32_t b = (uint32_t)bb;
     uint32_t m = 0;
     if (bb < t.nbuckets) m = t.cnt[b];
@@ -205,8 +212,8 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
     bool is_upd = false, is_ins = false, evicts = false;
     int new_slot = -1, evi = 0;
     uint64_t vkey = 0, vscore = 0;
-    uint32_t emask8 = 0, taken = 0, kloaded = 0, upd_bits = 0, ins_bits = 0;
-    uint64_t sc[SPL], kc[SPL];
+    uint32_t taken = 0, upd_bits = 0, ins_bits = 0;
+    uint64_t sc[SPL];
     bool full_after = false;
     uint32_t nev = 0;
 
@@ -216,13 +223,14 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
         is_upd = has && e.slot != kInsertSlot;
         is_ins = has && e.slot == kInsertSlot;
         const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
-        emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
+        const uint32_t emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
         const int occ = kSlots - gsum_i<GA>(__popc(emask8));
         const int nfree = kSlots - occ;
         upd_bits = (uint32_t)((__ballot(is_upd) >> gshift) & 0xFFFFu);
         ins_bits = (uint32_t)((__ballot(is_ins) >> gshift) & 0xFFFFu);
         const int ni = __popc(ins_bits);
         full_after = occ + ni >= kSlots;
+        taken = emask8;  // free slots are never victims
 
         // rank among the inserts: (score desc, key asc)
         int rank = 0;
@@ -231,18 +239,16 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
             const uint64_t kx = __shfl(e.key, x, GA);
             rank += (int)(((ins_bits >> x) & 1u) && (sx > e.score || (sx == e.score && kx < e.key)));
         }
-        // free slots of the bucket as a 128-bit mask
-        uint64_t elo = 0, ehi = 0;
-        if (ni > 0) {
+        if (ni > 0 && nfree > 0) {  // the first inserts take the free slots
+            uint64_t elo = 0, ehi = 0;
 #pragma unroll
             for (int q = 0; q < GA; ++q) {
                 const uint64_t mq = (uint64_t)__shfl((int)emask8, q, GA) & 0xFFull;
                 if (q < 8) elo |= mq << (8 * q);
                 else ehi |= mq << (8 * (q - 8));
             }
+            if (is_ins && rank < nfree) new_slot = nth_bit128(elo, ehi, rank);
         }
-        if (is_ins && rank < nfree) new_slot = nth_bit128(elo, ehi, rank);
-
         if (full_after) {  // scores of the bucket, with this call's updates applied
             const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
 #pragma unroll
@@ -269,20 +275,17 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
             uint64_t lm = ~0ull;
 #pragma unroll
             for (int q = 0; q < SPL; ++q)
-                if (!((emask8 | taken) >> q & 1u)) lm = sc[q] < lm ? sc[q] : lm;
+                if (!(taken >> q & 1u)) lm = sc[q] < lm ? sc[q] : lm;
             const uint64_t gm = gmin_u64<GA>(lm);
             if (!(s_in > gm)) break;  // rejected, and so is every later insert
             uint64_t lk = ~0ull;
             int lslot = -1;
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
-                if (!((emask8 | taken) >> q & 1u) && sc[q] == gm) {
-                    if (!(kloaded >> q & 1u)) {
-                        kc[q] = t.keys[eb + lane * SPL + q];
-                        kloaded |= 1u << q;
-                    }
-                    if (kc[q] < lk) {
-                        lk = kc[q];
+                if (!(taken >> q & 1u) && sc[q] == gm) {  // keys only for slots tied at the minimum
+                    const uint64_t kq = t.keys[eb + lane * SPL + q];
+                    if (kq < lk) {
+                        lk = kq;
                         lslot = lane * SPL + q;
                     }
                 }
@@ -309,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t tot = 0;
-            for (int q = 0; q < 64; ++q) {
+            for (int q = 0; q < kApplyGroups; ++q) {
                 s_off[q] = tot;
                 tot += s_nev[q];
             }
@@ -347,12 +350,7 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
             if (full_after) {
 #pragma unroll
                 for (int q = 0; q < SPL; ++q)
-                    if ((ns & 7) == q) {
-                        sc[q] = nsc;
-                        kc[q] = nk;
-                    }
-                kloaded |= 1u << (ns & 7);
-                emask8 &= ~(1u << (ns & 7));
+                    if ((ns & 7) == q) sc[q] = nsc;
             }
         }
     }
@@ -386,7 +384,8 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
             for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
         }
     }
-    // cached minimum of a full bucket (exact; every slot is occupied now)
+    // cached minimum of a full bucket (exact; every slot is occupied now).  Keys are read back
+    // only for slots tied at the minimum; the owning lane wrote any new key itself.
     if (full_after) {
         uint64_t lm = ~0ull;
 #pragma unroll
@@ -396,8 +395,8 @@ __global__ void __launch_bounds__(1024) k_apply_fast(TableView t, UpsertWs w, co
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
             if (sc[q] == gm) {
-                if (!(kloaded >> q & 1u)) kc[q] = t.keys[eb + lane * SPL + q];
-                lk = kc[q] < lk ? kc[q] : lk;
+                const uint64_t kq = t.keys[eb + lane * SPL + q];
+                lk = kq < lk ? kq : lk;
             }
         }
         const uint64_t gk = gmin_u64<GA>(lk);
@@ -664,7 +663,7 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
         case 16: launch_route<16>(t, w, n, keys, scores, clock, s); break;
         default: launch_route<8>(t, w, n, keys, scores, clock, s); break;
     }
-    k_apply_fast<<<(unsigned)((t.nbuckets + 63) / 64), 1024, 0, s>>>(t, w, vals, ev);
+    k_apply_fast<<<(unsigned)((t.nbuckets + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
     uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
     if (slow_blocks > 2048) slow_blocks = 2048;
     k_apply_slow<<<(unsigned)slow_blocks, 64, 0, s>>>(t, w, vals, ev);

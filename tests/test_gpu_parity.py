@@ -195,3 +195,20 @@ def test_api_errors_on_gpu():
     assert lib.cskv_table_bytes(128 * 3, 128, 8) == 0  # 3 buckets: not a power of two
     assert lib.cskv_table_bytes(128 * 4, 64, 8) == 0
     assert lib.cskv_table_bytes(128 * 4, 128, 6) == 0
+
+
+def test_launch_shapes_do_not_change_results():
+    """Every tuning variant (probe lanes per key, b2 prefetch, route lanes) gives bit-identical
+    outputs and tables, and matches the oracle."""
+    say("tuning variants")
+    for fg, pre, rg in [(4, 0, 8), (8, 1, 16), (16, 1, 4), (16, 0, 16)]:
+        tw = Twin(64 * 128, 8, "dual", "lru", seed=9)
+        tw.gpu.set_tuning(find_group=fg, find_prefetch_b2=pre, route_group=rg)
+        assert tw.gpu.get_tuning() == {"find_group": fg, "route_group": rg, "find_prefetch_b2": pre}
+        for rep in range(4):
+            tw.upsert(np_keys(70, 5000, rep * 3000), evict=True)
+            tw.find(np_keys(70, 20000))
+            tw.erase(np_keys(70, 500, rep * 700))
+        tw.check_table()
+    with pytest.raises(cskv.CskvError):
+        tw.gpu.set_tuning(find_group=5)
