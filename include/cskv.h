@@ -174,16 +174,65 @@ int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, u
  *  CSKV_TUNE_ROUTE_GROUP       lanes per key of the upsert routing kernel: 4, 8 (default) or 16
  *  CSKV_TUNE_FIND_PREFETCH_B2  1 = find loads both candidates' digest lines at once, 0 = b2 only
  *                              after a miss in b1 (default)
+ *  CSKV_TUNE_FIND_BLOCKS_PER_CU  grid of a program's merged find run: 0 (default) = one lane group
+ *                              per key; k in 1..64 = a persistent grid of k 256-thread blocks per
+ *                              compute unit striding over the run's keys
  * cskv_set_tuning returns CSKV_EINVAL for an unknown parameter or value; cskv_get_tuning returns
  * the current value, or -1.
  */
-enum { CSKV_TUNE_FIND_GROUP = 1, CSKV_TUNE_ROUTE_GROUP = 2, CSKV_TUNE_FIND_PREFETCH_B2 = 3 };
+enum {
+    CSKV_TUNE_FIND_GROUP = 1,
+    CSKV_TUNE_ROUTE_GROUP = 2,
+    CSKV_TUNE_FIND_PREFETCH_B2 = 3,
+    CSKV_TUNE_FIND_BLOCKS_PER_CU = 4
+};
 int cskv_set_tuning(cskv_table* table, int param, int value);
 int cskv_get_tuning(const cskv_table* table, int param);
 
-/* LRU logical clock (number of non-empty upsert calls so far, plus any value set below). */
+/*
+ * LRU logical clock: the number of non-empty upsert calls of an LRU table so far (plus any value
+ * set here).  It lives in table storage so that captured programs advance it on every replay.
+ * Both calls synchronize the device before reading or writing it.
+ */
 uint64_t cskv_clock(const cskv_table* table);
 int cskv_set_clock(cskv_table* table, uint64_t clock);
+
+/*
+ * Batched programs: many uneven find / insert_or_assign / insert_and_evict / erase batches on one
+ * table, enqueued by one call and optionally captured once as a hipGraph and replayed.
+ * Semantics are exactly those of issuing the same calls one by one, in order, on one stream:
+ *  - consecutive finds form a reader run (readers never conflict, Sec. 3.5 triple-group matrix)
+ *    and execute as ONE merged kernel over all their keys (a persistent grid when
+ *    CSKV_TUNE_FIND_BLOCKS_PER_CU > 0), with the table's tuning at the time the run's first
+ *    find was added;
+ *  - every upsert or erase is a serialization point (inserter group) run as its usual kernels.
+ * All pointers are recorded at add time and must stay valid (and unchanged in size) while the
+ * program is launched or replayed.  The program needs a device workspace of
+ * cskv_program_workspace_bytes bytes (256-byte aligned), given once with
+ * cskv_program_set_workspace, which also uploads the merged runs' descriptors (synchronously).
+ * cskv_program_capture records the program on `stream` (which must not be the NULL stream) into
+ * a graph and instantiates it; cskv_program_replay launches that graph.  Launch, capture and
+ * replay return CSKV_EINVAL before set_workspace; add after set_workspace returns CSKV_EINVAL.
+ */
+typedef struct cskv_program cskv_program;
+int cskv_program_create(cskv_program** out, cskv_table* table);
+int cskv_program_destroy(cskv_program* prog);
+int cskv_program_add_find(cskv_program* prog, uint64_t n, const uint64_t* d_keys, float* d_values_out,
+                          uint8_t* d_found, uint64_t* d_scores_out);
+int cskv_program_add_insert_or_assign(cskv_program* prog, uint64_t n, const uint64_t* d_keys,
+                                      const float* d_values, const uint64_t* d_scores, uint8_t* d_status);
+int cskv_program_add_insert_and_evict(cskv_program* prog, uint64_t n, const uint64_t* d_keys,
+                                      const float* d_values, const uint64_t* d_scores, uint8_t* d_status,
+                                      uint64_t* d_ev_keys, float* d_ev_values, uint64_t* d_ev_scores,
+                                      uint64_t* d_n_evicted);
+int cskv_program_add_erase(cskv_program* prog, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased);
+size_t cskv_program_workspace_bytes(const cskv_program* prog);
+int cskv_program_set_workspace(cskv_program* prog, void* d_ws, size_t ws_bytes);
+/* number of kernel-sequence segments: merged find runs + upserts + erases */
+uint32_t cskv_program_segments(const cskv_program* prog);
+int cskv_program_launch(cskv_program* prog, void* stream);
+int cskv_program_capture(cskv_program* prog, void* stream);
+int cskv_program_replay(cskv_program* prog, void* stream);
 
 /* number of buckets, value dim, mode and policy of a table (0 / -1 for NULL) */
 uint64_t cskv_num_buckets(const cskv_table* table);

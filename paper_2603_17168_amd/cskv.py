@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcskv.so")
 MODE = {"single": 1, "dual": 2}
 POLICY = {"custom": 0, "lru": 1, "lfu": 2}
 OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE = 0, 1, 2, 3
-TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3}
+TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
 
 _lib = None
@@ -53,6 +53,18 @@ def lib():
         "cskv_erase": (I, [P, U64, P, P, P, SZ, P]),
         "cskv_size": (I, [P, P, P]),
         "cskv_export": (I, [P, U64, U64, P, P, P, P, P, P]),
+        "cskv_program_create": (I, [ctypes.POINTER(P), P]),
+        "cskv_program_destroy": (I, [P]),
+        "cskv_program_add_find": (I, [P, U64, P, P, P, P]),
+        "cskv_program_add_insert_or_assign": (I, [P, U64, P, P, P, P]),
+        "cskv_program_add_insert_and_evict": (I, [P, U64, P, P, P, P, P, P, P, P]),
+        "cskv_program_add_erase": (I, [P, U64, P, P]),
+        "cskv_program_workspace_bytes": (SZ, [P]),
+        "cskv_program_set_workspace": (I, [P, P, SZ]),
+        "cskv_program_segments": (U32, [P]),
+        "cskv_program_launch": (I, [P, P]),
+        "cskv_program_capture": (I, [P, P]),
+        "cskv_program_replay": (I, [P, P]),
         "cskv_set_tuning": (I, [P, I, I]),
         "cskv_get_tuning": (I, [P, I]),
         "cskv_clock": (U64, [P]),
@@ -150,7 +162,8 @@ class Table:
         _check(lib().cskv_set_clock(self._h, c), "cskv_set_clock")
 
     def set_tuning(self, **kw):
-        """Launch-shape knobs (find_group, route_group, find_prefetch_b2); results never change."""
+        """Launch-shape knobs (find_group, route_group, find_prefetch_b2, find_blocks_per_cu); results
+        never change."""
         for k, v in kw.items():
             _check(lib().cskv_set_tuning(self._h, TUNE[k], int(v)), f"cskv_set_tuning({k}={v})")
 
@@ -246,3 +259,91 @@ class Table:
                                      _stream(self.device)), "cskv_export")
         n = int(c.item())
         return k[:n], (v[:n] if v is not None else None), s[:n], sl[:n]
+
+
+class Program:
+    """A batched program over one table (cskv_program_*): consecutive finds merge into one reader
+    run; upserts and erases are serialization points; the whole program can be captured once as a
+    hipGraph and replayed.  Tensors passed to add_* are kept alive by the program."""
+
+    def __init__(self, table: Table):
+        self.table = table
+        h = ctypes.c_void_p()
+        _check(lib().cskv_program_create(ctypes.byref(h), table._h), "cskv_program_create")
+        self._h = h
+        self._keep = []
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cskv_program_destroy(h)
+            self._h = None
+
+    def _k(self, t):
+        t = _as_i64(t, self.table.device)
+        self._keep.append(t)
+        return t
+
+    def _o(self, t):
+        if t is not None:
+            if not t.is_contiguous():
+                raise ValueError("program outputs must be contiguous")
+            self._keep.append(t)
+        return t
+
+    def add_find(self, keys, values_out, found_out, scores_out=None):
+        keys = self._k(keys)
+        _check(lib().cskv_program_add_find(self._h, keys.numel(), _ptr(keys), _ptr(self._o(values_out)),
+                                           _ptr(self._o(found_out)), _ptr(self._o(scores_out))),
+               "cskv_program_add_find")
+
+    def add_insert_or_assign(self, keys, values, scores=None, status_out=None):
+        keys = self._k(keys)
+        values = self._o(self.table._vals(values, keys.numel()))
+        scores = self._k(scores) if scores is not None else None
+        _check(lib().cskv_program_add_insert_or_assign(self._h, keys.numel(), _ptr(keys), _ptr(values), _ptr(scores),
+                                                       _ptr(self._o(status_out))),
+               "cskv_program_add_insert_or_assign")
+
+    def add_insert_and_evict(self, keys, values, scores, status, ev_keys, ev_values, ev_scores, n_evicted):
+        keys = self._k(keys)
+        values = self._o(self.table._vals(values, keys.numel()))
+        scores = self._k(scores) if scores is not None else None
+        _check(lib().cskv_program_add_insert_and_evict(
+            self._h, keys.numel(), _ptr(keys), _ptr(values), _ptr(scores), _ptr(self._o(status)),
+            _ptr(self._o(ev_keys)), _ptr(self._o(ev_values)), _ptr(self._o(ev_scores)), _ptr(self._o(n_evicted))),
+            "cskv_program_add_insert_and_evict")
+
+    def add_erase(self, keys, erased_out=None):
+        keys = self._k(keys)
+        _check(lib().cskv_program_add_erase(self._h, keys.numel(), _ptr(keys), _ptr(self._o(erased_out))),
+               "cskv_program_add_erase")
+
+    def finalize(self):
+        need = int(lib().cskv_program_workspace_bytes(self._h))
+        self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.table.device)
+        _check(lib().cskv_program_set_workspace(self._h, _ptr(self._ws), self._ws.numel()),
+               "cskv_program_set_workspace")
+        return self
+
+    @property
+    def segments(self) -> int:
+        return int(lib().cskv_program_segments(self._h))
+
+    def _s(self, stream):
+        s = stream if stream is not None else torch.cuda.current_stream(self.table.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def launch(self, stream=None):
+        with torch.cuda.device(self.table.device):
+            _check(lib().cskv_program_launch(self._h, self._s(stream)), "cskv_program_launch")
+
+    def capture(self, stream):
+        """Record the program on `stream` (a non-default torch.cuda.Stream) into a hipGraph."""
+        with torch.cuda.device(self.table.device):
+            _check(lib().cskv_program_capture(self._h, self._s(stream)), "cskv_program_capture")
+
+    def replay(self, stream=None):
+        with torch.cuda.device(self.table.device):
+            _check(lib().cskv_program_replay(self._h, self._s(stream)), "cskv_program_replay")

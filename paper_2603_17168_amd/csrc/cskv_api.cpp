@@ -7,17 +7,6 @@
 #include "../../include/cskv.h"
 #include "cskv_internal.h"
 
-struct cskv_table {
-    cskv::TableView view;
-    uint64_t capacity;
-    uint64_t clock;
-    int mode;
-    int policy;
-    int group;        // lanes per key of the find / erase probe kernels
-    int route_group;  // lanes per key of the upsert route kernel
-    int prefetch_b2;  // find loads both candidate digest lines at once
-};
-
 namespace cskv {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -31,6 +20,7 @@ StorageLayout storage_layout(uint64_t nb, uint32_t dim) {
     L.off_vals = o;   o = align256(o + nb * kSlots * (size_t)dim * 4);
     L.off_cnt = o;    o = align256(o + nb * 4);
     L.off_bmin = o;   o = align256(o + nb * 16);
+    L.off_clock = o;  o = align256(o + 8);
     L.total = o;
     return L;
 }
@@ -71,6 +61,8 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.off_il = o;      o = align256(o + nl * sizeof(OpEntry));
     L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
+    L.off_touched = o; o = align256(o + nslow * 4);
+    L.list_mode = n * 32 <= nb;  // a small batch: apply visits only the touched buckets
     L.total = o;
     return L;
 }
@@ -126,19 +118,27 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->view.vals = reinterpret_cast<float*>(base + L.off_vals);
     t->view.cnt = reinterpret_cast<uint32_t*>(base + L.off_cnt);
     t->view.bmin = reinterpret_cast<uint64_t*>(base + L.off_bmin);
+    t->view.clock = reinterpret_cast<uint64_t*>(base + L.off_clock);
     t->view.nbuckets = nb;
     t->view.bmask = (uint32_t)(nb - 1);
     t->view.dim = dim;
     t->view.dual = (mode == CSKV_MODE_DUAL);
     t->view.policy = score_policy;
     t->capacity = capacity;
-    t->clock = 0;
     t->mode = mode;
     t->policy = score_policy;
     t->group = 8;
     t->route_group = 8;
     t->prefetch_b2 = 0;
-    const int rc = hip_rc(launch_clear_table(t->view, as_stream(stream)));
+    t->blocks_per_cu = 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete t;
+        return CSKV_EHIP;
+    }
+    t->num_cus = cus;
+    int rc = hip_rc(launch_clear_table(t->view, as_stream(stream)));
+    if (rc == CSKV_OK) rc = hip_rc(launch_fill_zero(t->view.clock, 8, as_stream(stream)));
     if (rc != CSKV_OK) {
         delete t;
         return rc;
@@ -181,14 +181,17 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
                               table->prefetch_b2, as_stream(stream)));
 }
 
-static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
-                         const uint64_t* d_scores, uint8_t* d_status, const EvictOut& ev, void* d_ws,
-                         size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace cskv {
+
+int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    const uint64_t n = a.n;
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
-    if (!d_keys || !d_values || !d_ws) return CSKV_EINVAL;
-    if (table->policy == CSKV_SCORE_CUSTOM && !d_scores) return CSKV_EINVAL;
-    if (!aligned(d_keys, 8) || !aligned(d_values, 16) || !aligned(d_ws, 256) || (d_scores && !aligned(d_scores, 8)))
+    if (!a.keys || !a.vals || !d_ws) return CSKV_EINVAL;
+    if (table->policy == CSKV_SCORE_CUSTOM && !a.scores) return CSKV_EINVAL;
+    if (!aligned(a.keys, 8) || !aligned(a.vals, 16) || !aligned(d_ws, 256) || (a.scores && !aligned(a.scores, 8)))
         return CSKV_EINVAL;
     const UpsertLayout L = upsert_layout(n, table->view.nbuckets);
     if (ws_bytes < L.total) return CSKV_ENOMEM;
@@ -204,22 +207,34 @@ static int upsert_common(cskv_table* table, uint64_t n, const uint64_t* d_keys, 
     w.il = reinterpret_cast<OpEntry*>(b + L.off_il);
     w.ol = reinterpret_cast<OpEntry*>(b + L.off_ol);
     w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);
+    w.touched = reinterpret_cast<uint32_t*>(b + L.off_touched);
     w.P = L.P;
     w.logP = L.logP;
     w.cap = L.cap;
+    w.list_mode = L.list_mode;
     const size_t zero_bytes = table->policy == CSKV_SCORE_LFU ? L.off_zero_end_lfu : L.off_zero_end;
-    uint64_t clock = table->clock;
-    if (table->policy == CSKV_SCORE_LRU) clock += 1;
-    const int rc = hip_rc(launch_upsert(table->view, w, n, d_keys, d_values, d_scores, d_status, ev, clock, zero_bytes,
-                                        table->route_group, as_stream(stream)));
-    if (rc == CSKV_OK) table->clock = clock;
-    return rc;
+    return hip_rc(launch_upsert(table->view, w, n, a.keys, a.vals, a.scores, a.status, a.ev, zero_bytes,
+                                table->route_group, stream));
 }
+
+int enqueue_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_ws || !aligned(d_keys, 8) || !aligned(d_ws, 256)) return CSKV_EINVAL;
+    if (ws_bytes < erase_ws_bytes(n)) return CSKV_ENOMEM;
+    return hip_rc(launch_erase(table->view, n, d_keys, d_erased, reinterpret_cast<uint32_t*>(d_ws), table->group,
+                               stream));
+}
+
+}  // namespace cskv
+
+extern "C" {
 
 int cskv_insert_or_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
                           const uint64_t* d_scores, uint8_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
-    EvictOut ev{nullptr, nullptr, nullptr, nullptr};
-    return upsert_common(table, n, d_keys, d_values, d_scores, d_status, ev, d_ws, ws_bytes, stream);
+    UpsertArgs a{n, d_keys, d_values, d_scores, d_status, EvictOut{nullptr, nullptr, nullptr, nullptr}};
+    return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_insert_and_evict(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
@@ -231,18 +246,13 @@ int cskv_insert_and_evict(cskv_table* table, uint64_t n, const uint64_t* d_keys,
     if (!d_status || !d_ev_keys || !d_ev_values || !d_ev_scores || !d_n_evicted) return CSKV_EINVAL;
     if (!aligned(d_ev_keys, 8) || !aligned(d_ev_values, 16) || !aligned(d_ev_scores, 8) || !aligned(d_n_evicted, 8))
         return CSKV_EINVAL;
-    EvictOut ev{d_ev_keys, d_ev_values, d_ev_scores, d_n_evicted};
-    return upsert_common(table, n, d_keys, d_values, d_scores, d_status, ev, d_ws, ws_bytes, stream);
+    UpsertArgs a{n, d_keys, d_values, d_scores, d_status, EvictOut{d_ev_keys, d_ev_values, d_ev_scores, d_n_evicted}};
+    return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws, size_t ws_bytes,
                void* stream) {
-    if (!table || !n_ok(n)) return CSKV_EINVAL;
-    if (n == 0) return CSKV_OK;
-    if (!d_keys || !d_ws || !aligned(d_keys, 8) || !aligned(d_ws, 256)) return CSKV_EINVAL;
-    if (ws_bytes < erase_ws_bytes(n)) return CSKV_ENOMEM;
-    return hip_rc(launch_erase(table->view, n, d_keys, d_erased, reinterpret_cast<uint32_t*>(d_ws), table->group,
-                               as_stream(stream)));
+    return enqueue_erase(table, n, d_keys, d_erased, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_size(cskv_table* table, uint64_t* d_size, void* stream) {
@@ -276,6 +286,10 @@ int cskv_set_tuning(cskv_table* table, int param, int value) {
             if (value != 0 && value != 1) return CSKV_EINVAL;
             table->prefetch_b2 = value;
             return CSKV_OK;
+        case CSKV_TUNE_FIND_BLOCKS_PER_CU:
+            if (value < 0 || value > 64) return CSKV_EINVAL;
+            table->blocks_per_cu = value;
+            return CSKV_OK;
         default: return CSKV_EINVAL;
     }
 }
@@ -286,16 +300,23 @@ int cskv_get_tuning(const cskv_table* table, int param) {
         case CSKV_TUNE_FIND_GROUP: return table->group;
         case CSKV_TUNE_ROUTE_GROUP: return table->route_group;
         case CSKV_TUNE_FIND_PREFETCH_B2: return table->prefetch_b2;
+        case CSKV_TUNE_FIND_BLOCKS_PER_CU: return table->blocks_per_cu;
         default: return -1;
     }
 }
 
-uint64_t cskv_clock(const cskv_table* table) { return table ? table->clock : 0; }
+uint64_t cskv_clock(const cskv_table* table) {
+    if (!table) return 0;
+    uint64_t c = 0;
+    if (hipDeviceSynchronize() != hipSuccess) return 0;
+    if (hipMemcpy(&c, table->view.clock, 8, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+    return c;
+}
 
 int cskv_set_clock(cskv_table* table, uint64_t clock) {
     if (!table) return CSKV_EINVAL;
-    table->clock = clock;
-    return CSKV_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return CSKV_EHIP;
+    return hip_rc(hipMemcpy(table->view.clock, &clock, 8, hipMemcpyHostToDevice));
 }
 
 uint64_t cskv_num_buckets(const cskv_table* table) { return table ? table->view.nbuckets : 0; }

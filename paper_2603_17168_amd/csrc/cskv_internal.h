@@ -8,6 +8,7 @@
 //     vals   f32[B][128][dim]     value rows, addressed by (bucket, slot)
 //     cnt    u32[B]               operations routed to a bucket by the running call (0 between calls)
 //     bmin   u64[B][2]            (score, key) of a full bucket's minimum entry; key 0 = not known
+//     clock  u64                  LRU logical clock (device-resident so captured graphs advance it)
 //
 //   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity):
 //     zeroed on entry: dd {key u64, last u32, claim u32}[P], okey u64[P], ctr u32[64],
@@ -18,6 +19,7 @@
 //                                      (dedupe slot << 32 | input position), slot (0xFF = insert)
 //     ol OpEntry[P]                    list positions >= C, hashed on (bucket, position) via okey
 //     slow u32[min(n, B)]              buckets with more operations than the fast path takes
+//     touched u32[min(n, B)]           buckets that received an operation (small batches only)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,7 +33,7 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint8_t kInsertSlot = 0xFF;
 constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
-enum Counter { kCtrSlow = 0 };
+enum Counter { kCtrSlow = 0, kCtrTouched = 1 };
 
 struct TableView {
     uint8_t* dig;
@@ -40,6 +42,7 @@ struct TableView {
     float* vals;
     uint32_t* cnt;
     uint64_t* bmin;
+    uint64_t* clock;
     uint64_t nbuckets;
     uint32_t bmask;  // nbuckets - 1
     uint32_t dim;
@@ -71,9 +74,21 @@ struct UpsertWs {
     OpEntry* il;
     OpEntry* ol;
     uint32_t* slow;
+    uint32_t* touched;
     uint64_t P;
     int logP;
-    uint32_t cap;  // inline operations per bucket
+    uint32_t cap;    // inline operations per bucket
+    int list_mode;   // apply visits only the touched buckets (small batches)
+};
+
+// one batch of a merged run of finds (reader group): keys [begin, begin + n) of the run
+struct FindDesc {
+    const uint64_t* keys;
+    float* out;
+    uint8_t* found;
+    uint64_t* scores;
+    uint64_t begin;
+    uint64_t n;
 };
 
 struct EvictOut {
@@ -84,15 +99,16 @@ struct EvictOut {
 };
 
 struct StorageLayout {
-    size_t off_dig, off_keys, off_scores, off_vals, off_cnt, off_bmin, total;
+    size_t off_dig, off_keys, off_scores, off_vals, off_cnt, off_bmin, off_clock, total;
 };
 
 struct UpsertLayout {
     size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_zero_end, off_zero_end_lfu;
-    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, total;
+    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, off_touched, total;
     uint64_t P;
     int logP;
     uint32_t cap;
+    int list_mode;
 };
 
 StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim);
@@ -104,13 +120,44 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_clear_table(const TableView& t, hipStream_t s);
 hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
                        uint64_t* scores_out, int group, int prefetch_b2, hipStream_t s);
+hipError_t launch_find_multi(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, int group,
+                             int prefetch_b2, unsigned blocks, hipStream_t s);
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
                          const float* vals, const uint64_t* scores, uint8_t* status, const EvictOut& ev,
-                         uint64_t clock, size_t zero_bytes, int group, hipStream_t s);
+                         size_t zero_bytes, int group, hipStream_t s);
 hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                         uint32_t* ws_slot, int group, hipStream_t s);
 hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s);
 hipError_t launch_export(const TableView& t, uint64_t b0, uint64_t b1, uint64_t* keys, float* vals,
                          uint64_t* scores, uint64_t* slots, uint64_t* count, hipStream_t s);
 
+// enqueue helpers shared by the single-call C ABI and the batched program (return CSKV_* codes)
+struct UpsertArgs {
+    uint64_t n;
+    const uint64_t* keys;
+    const float* vals;
+    const uint64_t* scores;
+    uint8_t* status;
+    EvictOut ev;
+};
+
+}  // namespace cskv
+
+// the C ABI's opaque table object
+struct cskv_table {
+    cskv::TableView view;
+    uint64_t capacity;
+    int mode;
+    int policy;
+    int group;          // lanes per key of the find / erase probe kernels
+    int route_group;    // lanes per key of the upsert route kernel
+    int prefetch_b2;    // find loads both candidate digest lines at once
+    int blocks_per_cu;  // persistent grid of merged find runs: blocks per compute unit (0 = one group per key)
+    int num_cus;
+};
+
+namespace cskv {
+int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
+int enqueue_erase(cskv_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased, void* ws, size_t ws_bytes,
+                  hipStream_t s);
 }  // namespace cskv

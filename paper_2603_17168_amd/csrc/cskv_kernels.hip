@@ -45,13 +45,8 @@ hipError_t launch_clear_table(const TableView& t, hipStream_t s) {
 // find (Alg. 1; dual mode probes b2 after a miss in b1).  With PRE the b2 line is loaded
 // together with the b1 line (one round trip less on b2 hits and misses, 128 B more per b1 hit).
 template <int G, bool PRE>
-__global__ void __launch_bounds__(256) k_find(TableView t, uint64_t n, const uint64_t* __restrict__ keys,
-                                              float* __restrict__ out, uint8_t* __restrict__ found,
-                                              uint64_t* __restrict__ scores_out) {
-    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    if (i >= n) return;
-    const int lane = glane<G>();
-    const uint64_t k = keys[i];
+__device__ __forceinline__ void find_one(const TableView& t, uint64_t k, float* __restrict__ out_row,
+                                         uint8_t* __restrict__ found, uint64_t* __restrict__ score_out, int lane) {
     int slot = -1;
     uint32_t b = 0;
     if (!reserved_key(k)) {
@@ -69,14 +64,63 @@ __global__ void __launch_bounds__(256) k_find(TableView t, uint64_t n, const uin
     }
     if (slot >= 0) {
         const size_t e = (size_t)b * kSlots + slot;
-        copy_row<G>(out + i * t.dim, t.vals + e * t.dim, t.dim, lane);
+        copy_row<G>(out_row, t.vals + e * t.dim, t.dim, lane);
         if (lane == 0) {
-            found[i] = 1;
-            if (scores_out) scores_out[i] = t.scores[e];
+            *found = 1;
+            if (score_out) *score_out = t.scores[e];
         }
     } else if (lane == 0) {
-        found[i] = 0;
+        *found = 0;
     }
+}
+
+template <int G, bool PRE>
+__global__ void __launch_bounds__(256) k_find(TableView t, uint64_t n, const uint64_t* __restrict__ keys,
+                                              float* __restrict__ out, uint8_t* __restrict__ found,
+                                              uint64_t* __restrict__ scores_out) {
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= n) return;
+    find_one<G, PRE>(t, keys[i], out + i * t.dim, found + i, scores_out ? scores_out + i : nullptr, glane<G>());
+}
+
+// a merged run of find batches (readers never conflict, Sec. 3.5): a persistent grid strides over
+// the concatenated keys; each key finds its batch by binary search over the batch offsets
+template <int G, bool PRE>
+__global__ void __launch_bounds__(256) k_find_multi(TableView t, const FindDesc* __restrict__ d, uint32_t nd,
+                                                    uint64_t total) {
+    const uint64_t ngroups = ((uint64_t)gridDim.x * blockDim.x) / G;
+    const int lane = glane<G>();
+    for (uint64_t gi = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; gi < total; gi += ngroups) {
+        uint32_t lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (d[mid].begin <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        const FindDesc& q = d[lo];
+        const uint64_t i = gi - q.begin;
+        find_one<G, PRE>(t, q.keys[i], q.out + i * t.dim, q.found + i, q.scores ? q.scores + i : nullptr, lane);
+    }
+}
+
+template <int G>
+static void launch_find_multi_g(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, bool pre,
+                                unsigned blocks, hipStream_t s) {
+    if (pre) k_find_multi<G, true><<<blocks, 256, 0, s>>>(t, d, nd, total);
+    else k_find_multi<G, false><<<blocks, 256, 0, s>>>(t, d, nd, total);
+}
+
+hipError_t launch_find_multi(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, int group,
+                             int prefetch_b2, unsigned blocks, hipStream_t s) {
+    if (total == 0 || nd == 0) return hipSuccess;
+    const bool pre = prefetch_b2 != 0;
+    if (blocks == 0) blocks = blocks_for(total * (uint64_t)group, 256);
+    switch (group) {
+        case 4: launch_find_multi_g<4>(t, d, nd, total, pre, blocks, s); break;
+        case 16: launch_find_multi_g<16>(t, d, nd, total, pre, blocks, s); break;
+        default: launch_find_multi_g<8>(t, d, nd, total, pre, blocks, s); break;
+    }
+    return hipGetLastError();
 }
 
 template <int G>

@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_
 // ------------------------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                               const uint64_t* __restrict__ scores, uint64_t clock) {
+                                               const uint64_t* __restrict__ scores) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     if (i >= n) return;
     const int lane = glane<G>();
@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     const DedupeEntry de = w.dd[p];
     if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
     const uint64_t k = keys[i];
+    const uint64_t clock = *t.clock + 1;  // LRU: this call's clock (advanced after routing)
     const KeyHash h = hash_key(t, k);
     const bool two = h.b2 != h.b1;
     LineSeg<G> s1, s2;
@@ -156,6 +157,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     }
     if (lane == 0) {
         const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
+        if (w.list_mode && r == 0) w.touched[atomicAdd(w.ctr + kCtrTouched, 1u)] = tgt;
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         if (r < w.cap) {
             store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot);
@@ -197,7 +199,8 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     const int g = threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     const int gshift = (threadIdx.x & 63) & ~(GA - 1);
-    const uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
+    uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
+    if (w.list_mode) bb = bb < w.ctr[kCtrTouched] ? w.touched[bb] : t.nbuckets;
     const uint32_t b = (uint32_t)bb;
     uint32_t m = 0;
     if (bb < t.nbuckets) m = t.cnt[b];
@@ -420,6 +423,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     __shared__ unsigned long long ev_base_s;
 
     const int lane = threadIdx.x;
+    if (blockIdx.x == 0 && lane == 0 && t.policy == 1) *t.clock += 1;  // routing has read the clock
     const uint32_t nslow = w.ctr[kCtrSlow];
     const uint32_t chunks = t.dim >> 2;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -647,23 +651,24 @@ __global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t*
 
 template <int G>
 static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
-                         uint64_t clock, hipStream_t s) {
-    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, clock);
+                         hipStream_t s) {
+    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores);
 }
 
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
-                         const uint64_t* scores, uint8_t* status, const EvictOut& ev, uint64_t clock, size_t zero_bytes,
-                         int group, hipStream_t s) {
+                         const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
+                         hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipError_t e = launch_fill_zero(w.dd, zero_bytes, s);
     if (e != hipSuccess) return e;
     k_dedupe<<<blocks_for(n, 256), 256, 0, s>>>(t, w, n, keys, scores, ev.count);
     switch (group) {
-        case 4: launch_route<4>(t, w, n, keys, scores, clock, s); break;
-        case 16: launch_route<16>(t, w, n, keys, scores, clock, s); break;
-        default: launch_route<8>(t, w, n, keys, scores, clock, s); break;
+        case 4: launch_route<4>(t, w, n, keys, scores, s); break;
+        case 16: launch_route<16>(t, w, n, keys, scores, s); break;
+        default: launch_route<8>(t, w, n, keys, scores, s); break;
     }
-    k_apply_fast<<<(unsigned)((t.nbuckets + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
+    const uint64_t visit = w.list_mode ? (n < t.nbuckets ? n : t.nbuckets) : t.nbuckets;
+    k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
     uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
     if (slow_blocks > 2048) slow_blocks = 2048;
     k_apply_slow<<<(unsigned)slow_blocks, 64, 0, s>>>(t, w, vals, ev);

@@ -164,3 +164,56 @@ def poisson_arrivals(stream: int, n: int, rate_per_s: float) -> np.ndarray:
     """Arrival times (seconds) of a Poisson process: cumulative exponential gaps."""
     u = uniform01(stream, n).numpy()
     return np.cumsum(-np.log1p(-u) / rate_per_s)
+
+
+def batch_schedule(stream: int, nbatches: int, lo: int, hi: int, mix=(0.70, 0.25, 0.05)):
+    """Uneven batch program: sizes log-uniform in [lo, hi], ops drawn find / insert_or_assign /
+    erase with probabilities `mix`.  Returns a list of (op, size) with op in {"find", "upsert",
+    "erase"}."""
+    u = uniform01(stream, 2 * nbatches).numpy()
+    sizes = np.floor(np.exp(np.log(lo) + u[:nbatches] * (np.log(hi) - np.log(lo)))).astype(np.int64)
+    sizes = np.clip(sizes, lo, hi)
+    ops = []
+    c1, c2 = mix[0], mix[0] + mix[1]
+    for i in range(nbatches):
+        r = u[nbatches + i]
+        ops.append(("find" if r < c1 else "upsert" if r < c2 else "erase", int(sizes[i])))
+    return ops
+
+
+def program_inputs(schedule, dim: int, resident: torch.Tensor, fresh_stream: int, miss_stream: int, seed: int,
+                   device="cpu"):
+    """Device inputs and output buffers for a batch schedule (see :func:`batch_schedule`).
+
+    find: half the keys drawn with replacement from `resident`, half never-inserted keys from
+    `miss_stream`, shuffled; upsert: fresh keys from `fresh_stream` with rows from `value_rows`;
+    erase: keys drawn from `resident`.  Returns a list of dicts with the op, its inputs and
+    freshly allocated outputs."""
+    out = []
+    fresh_ctr = 0
+    miss_ctr = 0
+    nres = resident.numel()
+    for j, (op, n) in enumerate(schedule):
+        d = {"op": op, "n": n}
+        if op == "find":
+            h = n // 2
+            idx = randint(10_000 + j, n - h, nres, device=device)
+            miss = keys(miss_stream, h, miss_ctr, device=device)
+            miss_ctr += h
+            q = torch.cat([resident.to(device)[idx], miss])
+            perm = torch.argsort(uniform_u64(20_000 + j, n, device=device))
+            d["keys"] = q[perm].contiguous()
+            d["out"] = torch.zeros((n, dim), dtype=torch.float32, device=device)
+            d["flag"] = torch.empty(n, dtype=torch.uint8, device=device)
+        elif op == "upsert":
+            k = keys(fresh_stream, n, fresh_ctr, device=device)
+            fresh_ctr += n
+            d["keys"] = k
+            d["values"] = value_rows(seed, k, dim)
+            d["flag"] = torch.empty(n, dtype=torch.uint8, device=device)
+        else:
+            idx = randint(30_000 + j, n, nres, device=device)
+            d["keys"] = resident.to(device)[idx].contiguous()
+            d["flag"] = torch.empty(n, dtype=torch.uint8, device=device)
+        out.append(d)
+    return out

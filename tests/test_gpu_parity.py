@@ -204,7 +204,8 @@ def test_launch_shapes_do_not_change_results():
     for fg, pre, rg in [(4, 0, 8), (8, 1, 16), (16, 1, 4), (16, 0, 16)]:
         tw = Twin(64 * 128, 8, "dual", "lru", seed=9)
         tw.gpu.set_tuning(find_group=fg, find_prefetch_b2=pre, route_group=rg)
-        assert tw.gpu.get_tuning() == {"find_group": fg, "route_group": rg, "find_prefetch_b2": pre}
+        got = tw.gpu.get_tuning()
+        assert (got["find_group"], got["route_group"], got["find_prefetch_b2"]) == (fg, rg, pre)
         for rep in range(4):
             tw.upsert(np_keys(70, 5000, rep * 3000), evict=True)
             tw.find(np_keys(70, 20000))
