@@ -26,8 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from paper_2603_17168_amd import cskv  # noqa: E402
-from paper_2603_17168_amd.workload import keys as gen_keys, randint, value_rows  # noqa: E402
+from paper_2603_17168_amd import autotune as tuner  # noqa: E402
+from paper_2603_17168_amd import cskv, serve  # noqa: E402
+from paper_2603_17168_amd.workload import (Zipf, batch_schedule, keys as gen_keys, lognormal_sizes,  # noqa: E402
+                                            poisson_arrivals, program_inputs, randint, uniform01, value_rows)
 
 METRIC = "find & upsert B-KV/s at load 0.5–1.0, % of HBM peak; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
@@ -113,6 +115,142 @@ def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3):
     return tuning
 
 
+def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, hi=1 << 20):
+    """Batched programs: 256 uneven batches (log-uniform 1K..1M keys, 70/25/5 find / upsert /
+    erase) on a 2^26-slot dim-32 LRU table prefilled to load 0.9, run three ways from the same
+    starting table: plain per-batch calls, one program launch (merged reader runs, autotuned
+    shapes per size class), and the program captured as a hipGraph and replayed."""
+    cap = 1 << log2_cap
+    base = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
+    offered, size = fill(base, load, 1 << 20, dim, 2, 0, dev)
+    resident = gen_keys(2, int(size), 0, device=dev)  # below first eviction every inserted key is resident
+    log(f"batched: prefilled {size} ({size / cap:.3f})")
+    sched = batch_schedule(21, nbatches, lo, hi)
+    ops = program_inputs(sched, dim, resident, fresh_stream=22, miss_stream=23, seed=11, device=dev)
+    total = sum(n for _, n in sched)
+    snap = base.storage.clone()
+    # autotune shapes per size class on the prefilled table (restored afterwards)
+    q = {c: resident[: tuner.CLASS_SIZE[c]] for c in ("small", "medium", "large")}
+    fr = {c: gen_keys(24, tuner.CLASS_SIZE[c], 0, device=dev) for c in ("small", "medium", "large")}
+    tuning = tuner.merge(tuner.tune_find(base, q), tuner.tune_route(base, fr))
+    log(f"batched tuning: {tuning}")
+
+    def restore():
+        base.storage.copy_(snap)
+        torch.cuda.synchronize()
+
+    def run_plain():
+        for d in ops:
+            tuner.apply(base, tuning, d["n"])
+            if d["op"] == "find":
+                base.find(d["keys"], values_out=d["out"], found_out=d["flag"], want_scores=False)
+            elif d["op"] == "upsert":
+                base.insert_or_assign(d["keys"], d["values"], status_out=d["flag"])
+            else:
+                base.erase(d["keys"], erased_out=d["flag"])
+
+    def outputs():
+        return [(d["flag"].clone(), d["out"][d["flag"].bool()].clone() if "out" in d else None) for d in ops]
+
+    res = {}
+    restore()
+    run_plain()  # warm
+    restore()
+    t0 = time.perf_counter()
+    run_plain()
+    torch.cuda.synchronize()
+    res["plain_s"] = time.perf_counter() - t0
+    ref = outputs()
+    prog = cskv.Program(base)
+    for d in ops:
+        tuner.apply(base, tuning, d["n"])
+        if d["op"] == "find":
+            prog.add_find(d["keys"], d["out"], d["flag"])
+        elif d["op"] == "upsert":
+            prog.add_insert_or_assign(d["keys"], d["values"], None, d["flag"])
+        else:
+            prog.add_erase(d["keys"], d["flag"])
+    prog.finalize()
+    restore()
+    t0 = time.perf_counter()
+    prog.launch()
+    torch.cuda.synchronize()
+    res["program_s"] = time.perf_counter() - t0
+    same = all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
+               for a, b in zip(ref, outputs()))
+    stream = torch.cuda.Stream(device=dev)
+    prog.capture(stream)
+    restore()
+    prog.replay(stream)  # warm
+    stream.synchronize()
+    restore()
+    t0 = time.perf_counter()
+    prog.replay(stream)
+    stream.synchronize()
+    res["graph_s"] = time.perf_counter() - t0
+    same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
+                        for a, b in zip(ref, outputs()))
+    out = {"workload": f"{nbatches} batches log-uniform {lo}..{hi} keys, 70/25/5 find/insert_or_assign/erase, "
+                       f"2^{log2_cap} slots dim {dim} LRU at load {load}",
+           "total_keys": total, "segments": prog.segments,
+           "plain_bkvs": round(total / res["plain_s"] / 1e9, 3),
+           "program_bkvs": round(total / res["program_s"] / 1e9, 3),
+           "graph_bkvs": round(total / res["graph_s"] / 1e9, 3),
+           "graph_vs_plain": round(res["plain_s"] / res["graph_s"], 3),
+           "identical_outputs": bool(same), "tuning": tuning}
+    del prog, base, snap, ops
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(0.5, 0.8)):
+    """Serving loop: a 2^28-slot dim-128 LRU table (~142 GB) prefilled with ranks 1..2^28;
+    requests of lognormal(4096, 1.0) keys clipped to 256..65536, 90 % find / 10 %
+    insert_and_evict, Zipf(1.1) keys over 2^34, arriving as a Poisson process at 50 % and 80 % of
+    the plain FIFO server's measured saturation rate; p50/p99 latency of the continuous-batching
+    server and of the plain server (one request per launch, one launch in flight)."""
+    cap = 1 << log2_cap
+    t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
+    b = 1 << 20
+    for s0 in range(0, cap, b):
+        k = torch.arange(1 + s0, 1 + s0 + b, dtype=torch.int64, device=dev)
+        t.insert_or_assign(k, value_rows(13, k, dim), want_status=False)
+    size = t.size()
+    log(f"serving: prefilled {size} ({size / cap:.3f})")
+    sizes = lognormal_sizes(31, nreq, 4096.0, 1.0, 256, 65536)
+    ops = np.where(uniform01(32, nreq).numpy() < 0.9, serve.REQ_FIND, serve.REQ_INSERT_AND_EVICT)
+    keys = Zipf(1.1, 1 << 34).sample_device(33, int(sizes.sum()), dev)
+    ins = ops == serve.REQ_INSERT_AND_EVICT
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    ins_keys = torch.cat([keys[off[i]:off[i + 1]] for i in range(nreq) if ins[i]])
+    vals = value_rows(14, ins_keys, dim)
+    log(f"serving: {nreq} requests, {int(sizes.sum())} keys")
+    zero = np.zeros(nreq)
+    tr = serve.Trace(t, ops, sizes, keys, vals, zero)
+    st_plain, _ = serve.serve(t, tr, budget, max_inflight_groups=1, max_merge=1, realtime=False)
+    sat = nreq / st_plain["wall_s"]
+    st_cb, _ = serve.serve(t, tr, budget, max_inflight_groups=2, max_merge=64, realtime=False)
+    out = {"workload": f"2^{log2_cap} slots dim {dim} LRU ({size / cap:.3f} full), {nreq} requests lognormal(4096, 1.0) "
+                       f"keys in [256, 65536], 90/10 find/insert_and_evict, Zipf(1.1) over 2^34, budget {budget >> 30} GiB",
+           "plain_saturation_qps": round(sat, 1), "batched_saturation_qps": round(nreq / st_cb["wall_s"], 1),
+           "levels": {}}
+    for frac in loads:
+        qps = frac * sat
+        arr = poisson_arrivals(40 + int(frac * 100), nreq, qps)
+        row = {"qps": round(qps, 1)}
+        for name, mi, mm in (("continuous_batching", 2, 64), ("plain_fifo", 1, 1)):
+            trq = serve.Trace(t, ops, sizes, keys, vals, arr)
+            st, times = serve.serve(t, trq, budget, max_inflight_groups=mi, max_merge=mm, realtime=True)
+            lat = times["latency_s"][nreq // 10:]  # after warm-up
+            row[name] = {**{k: round(v, 4) for k, v in serve.percentiles_ms(lat).items()},
+                         "launches": int(st["groups"]), "deferred": int(st["deferred_for_memory"])}
+            log(f"serving qps {qps:.0f} {name}: {row[name]}")
+        out["levels"][f"{frac:.2f}"] = row
+    del t, keys, vals, tr
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
     """Sequential C oracle (one thread) on a sample: a 2^22-slot dual LRU table filled to each
     load factor (untimed), then the step's three ops on 2^18-key batches, timed."""
@@ -158,6 +296,9 @@ def main():
     ap.add_argument("--log2-batch", type=int, default=20)
     ap.add_argument("--loads", type=str, default="0.5,0.75,0.9,1.0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
@@ -292,6 +433,20 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"k_find<{tuning['find_group']},{bool(tuning['find_prefetch_b2'])}>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
+    del levels, q100, q50, fresh, rows, outs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched programs")
+        out["batched"] = bench_batched(dev)
+    if not args.no_serving:
+        log("serving loop")
+        out["serving"] = bench_serving(dev, nreq=args.serve_requests)
+        lv = out["serving"]["levels"]
+        if lv:
+            top = lv[max(lv)]["continuous_batching"]
+            out["latency_ms"]["served_p50"] = top["p50"]
+            out["latency_ms"]["served_p99"] = top["p99"]
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the sequential oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(loads)

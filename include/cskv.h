@@ -243,6 +243,64 @@ int cskv_policy(const cskv_table* table);
 /* static text for a return code */
 const char* cskv_strerror(int code);
 
+/*
+ * Serving loop (continuous batching).  cskv_serve_trace runs a trace of requests against one
+ * table, in real time when cfg->realtime is 1 (a request exists only from its arrival time on)
+ * or with every request present at time 0 otherwise, and returns when all have completed.
+ *  - Admission: requests are admitted in arrival order while their footprint (input and output
+ *    bytes) fits into cfg->arena_budget_bytes together with every admitted, unfinished request;
+ *    a request that does not fit waits (it is deferred, never failed); a request larger than
+ *    the whole budget is refused with CSKV_EINVAL before anything runs.
+ *  - Execution: admitted requests are launched in admission order on `stream` whenever fewer
+ *    than cfg->max_inflight_groups groups are on the GPU.  Consecutive admitted finds merge into
+ *    one reader launch of at most cfg->max_merge (<= 64) requests; each insert_and_evict is a
+ *    serialization point (inserter group, Sec. 3.5).  New groups are enqueued while earlier ones
+ *    run, so their work overlaps on the device.  The result of every request is exactly that of
+ *    issuing the requests alone, one by one, in admission order.
+ *  - Outputs go to the request's d_* result pointers; when those are NULL they go to a ring
+ *    arena in the workspace (of arena_budget_bytes) and are recycled after completion.
+ *  - Times (seconds from the start of the trace, host clock): admit_s, launch_s, complete_s
+ *    (the host saw the group's completion event); seq is the admission order.
+ * Workspace: cskv_serve_workspace_bytes(table, max_request_keys, arena_budget_bytes), 256-byte
+ * aligned; max_request_keys bounds every request's n.
+ */
+enum { CSKV_REQ_FIND = 0, CSKV_REQ_INSERT_AND_EVICT = 1 };
+
+typedef struct cskv_request {
+    int op;              /* CSKV_REQ_* */
+    uint64_t n;
+    const uint64_t* d_keys;
+    const float* d_values;      /* insert_and_evict: n*dim rows */
+    const uint64_t* d_scores;   /* as for cskv_insert_and_evict */
+    float* d_values_out;        /* find rows (nullable: arena) */
+    uint8_t* d_flags;           /* find: found; insert: status (nullable: arena) */
+    uint64_t* d_ev_keys;        /* insert results (nullable together: arena) */
+    float* d_ev_values;
+    uint64_t* d_ev_scores;
+    uint64_t* d_n_evicted;
+    double arrival_s;
+    /* written by the server */
+    double admit_s, launch_s, complete_s;
+    uint64_t seq;
+    uint32_t group;
+} cskv_request;
+
+typedef struct cskv_serve_config {
+    uint64_t arena_budget_bytes;
+    uint32_t max_inflight_groups;
+    uint32_t max_merge;
+    int realtime;
+} cskv_serve_config;
+
+typedef struct cskv_serve_stats {
+    uint64_t completed, groups, reader_launches, inserter_launches, deferred_for_memory, peak_inflight_bytes;
+    double wall_s;
+} cskv_serve_stats;
+
+size_t cskv_serve_workspace_bytes(const cskv_table* table, uint64_t max_request_keys, uint64_t arena_budget_bytes);
+int cskv_serve_trace(cskv_table* table, cskv_request* reqs, uint64_t nreq, const cskv_serve_config* cfg,
+                     void* d_ws, size_t ws_bytes, void* stream, cskv_serve_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,14 @@ struct FindDesc {
     uint64_t n;
 };
 
+// a small merged run passed by value as kernel arguments (no descriptor upload)
+constexpr int kMaxArgDescs = 64;
+struct FindDescArgs {
+    FindDesc d[kMaxArgDescs];
+    uint32_t nd;
+    uint64_t total;
+};
+
 struct EvictOut {
     uint64_t* keys;
     float* vals;
@@ -122,6 +130,7 @@ hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, flo
                        uint64_t* scores_out, int group, int prefetch_b2, hipStream_t s);
 hipError_t launch_find_multi(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, int group,
                              int prefetch_b2, unsigned blocks, hipStream_t s);
+hipError_t launch_find_args(const TableView& t, const FindDescArgs& a, int group, int prefetch_b2, hipStream_t s);
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
                          const float* vals, const uint64_t* scores, uint8_t* status, const EvictOut& ev,
                          size_t zero_bytes, int group, hipStream_t s);

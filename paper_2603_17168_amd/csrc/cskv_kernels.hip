@@ -103,6 +103,34 @@ __global__ void __launch_bounds__(256) k_find_multi(TableView t, const FindDesc*
     }
 }
 
+// a merged run whose descriptors travel as kernel arguments (serving loop)
+template <int G, bool PRE>
+__global__ void __launch_bounds__(256) k_find_args(TableView t, FindDescArgs a) {
+    const uint64_t gi = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (gi >= a.total) return;
+    uint32_t lo = 0, hi = a.nd - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a.d[mid].begin <= gi) lo = mid;
+        else hi = mid - 1;
+    }
+    const FindDesc& q = a.d[lo];
+    const uint64_t i = gi - q.begin;
+    find_one<G, PRE>(t, q.keys[i], q.out + i * t.dim, q.found + i, q.scores ? q.scores + i : nullptr, glane<G>());
+}
+
+hipError_t launch_find_args(const TableView& t, const FindDescArgs& a, int group, int prefetch_b2, hipStream_t s) {
+    if (a.total == 0 || a.nd == 0) return hipSuccess;
+    const unsigned blocks = blocks_for(a.total * (uint64_t)group, 256);
+    const bool pre = prefetch_b2 != 0;
+    switch (group) {
+        case 4: pre ? k_find_args<4, true><<<blocks, 256, 0, s>>>(t, a) : k_find_args<4, false><<<blocks, 256, 0, s>>>(t, a); break;
+        case 16: pre ? k_find_args<16, true><<<blocks, 256, 0, s>>>(t, a) : k_find_args<16, false><<<blocks, 256, 0, s>>>(t, a); break;
+        default: pre ? k_find_args<8, true><<<blocks, 256, 0, s>>>(t, a) : k_find_args<8, false><<<blocks, 256, 0, s>>>(t, a); break;
+    }
+    return hipGetLastError();
+}
+
 template <int G>
 static void launch_find_multi_g(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, bool pre,
                                 unsigned blocks, hipStream_t s) {

@@ -126,6 +126,26 @@ class Zipf:
         t = np.maximum(y * (1.0 - self.a), -1.0 + 1e-300)
         return np.exp(np.log1p(t) / (1.0 - self.a))
 
+    def sample_device(self, stream: int, n: int, device) -> torch.Tensor:
+        """The same algorithm in float64 torch ops on `device` (int64 ranks); seeded, but not
+        guaranteed to equal :meth:`sample` draw for draw (libm rounding may differ)."""
+        a = self.a
+        H = lambda x: torch.expm1((1.0 - a) * torch.log(x)) / (1.0 - a)
+        Hinv = lambda y: torch.exp(torch.log1p(torch.clamp(y * (1.0 - a), min=-1.0 + 1e-300)) / (1.0 - a))
+        out = torch.empty(n, dtype=torch.int64, device=device)
+        todo = torch.arange(n, device=device)
+        ctr = 0
+        while todo.numel():
+            u = uniform01(stream, todo.numel(), start=ctr, device=device)
+            ctr += todo.numel()
+            u = self.h_n + u * (self.h_x1 - self.h_n)
+            x = Hinv(u)
+            k = torch.clamp(torch.floor(x + 0.5), 1, self.N)
+            ok = (k - x <= self.s) | (u >= H(k + 0.5) - torch.exp(-a * torch.log(k)))
+            out[todo[ok]] = k[ok].to(torch.int64)
+            todo = todo[~ok]
+        return out
+
     def sample(self, stream: int, n: int) -> np.ndarray:
         out = np.empty(n, dtype=np.uint64)
         todo = np.arange(n)
