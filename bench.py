@@ -79,7 +79,7 @@ def clone(src: cskv.Table) -> cskv.Table:
     return dst
 
 
-def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3):
+def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3, tune_route=True):
     """Pick find group/prefetch and route group by HIP-event timing on sample batches."""
     def timed(fn):
         ts = []
@@ -96,14 +96,17 @@ def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3):
     best = None
     for g in (4, 8, 16):
         for pre in (0, 1):
-            t.set_tuning(find_group=g, find_prefetch_b2=pre)
-            ms = timed(lambda: (t.find(q100, values_out=outs, found_out=found, want_scores=False),
-                                t.find(q50, values_out=outs, found_out=found, want_scores=False)))
-            log(f"autotune find group {g} prefetch {pre}: {ms:.3f} ms")
-            if best is None or ms < best[0]:
-                best = (ms, g, pre)
-    tuning = {"find_group": best[1], "find_prefetch_b2": best[2]}
+            for pairs in (0, 1):
+                t.set_tuning(find_group=g, find_prefetch_b2=pre, find_pairs=pairs)
+                ms = timed(lambda: (t.find(q100, values_out=outs, found_out=found, want_scores=False),
+                                    t.find(q50, values_out=outs, found_out=found, want_scores=False)))
+                log(f"autotune find group {g} prefetch {pre} pairs {pairs}: {ms:.3f} ms")
+                if best is None or ms < best[0]:
+                    best = (ms, g, pre, pairs)
+    tuning = {"find_group": best[1], "find_prefetch_b2": best[2], "find_pairs": best[3]}
     t.set_tuning(**tuning)
+    if not tune_route:
+        return tuning
     best_r = None
     for g in (8, 16):
         t.set_tuning(route_group=g)
@@ -347,11 +350,16 @@ def main():
         lv.t.workspace(cskv.OP_ERASE, batch)
     torch.cuda.synchronize()
 
-    # autotune launch shapes (results do not depend on them) on the first table
-    tuning = autotune(levels[0].t, q100[0], q50[0], gen_keys(700, batch, 0, device=dev), rows, outs, found, status,
-                      erased)
-    for lv in levels:
-        lv.t.set_tuning(**tuning)
+    # autotune launch shapes (results do not depend on them) on every table
+    tunings = []
+    for li, lv in enumerate(levels):
+        tu = autotune(lv.t, q100[li], q50[li], gen_keys(700 + li, batch, 0, device=dev), rows, outs, found, status,
+                      erased, tune_route=(li == 0))
+        tunings.append(tu)
+    for lv, tu in zip(levels, tunings):
+        tu.setdefault("route_group", tunings[0]["route_group"])
+        lv.t.set_tuning(**tu)
+    tuning = {f"{lv.target:.2f}": tu for lv, tu in zip(levels, tunings)}
     log(f"tuning: {tuning}")
 
     ev = {}
@@ -430,7 +438,7 @@ def main():
         "latency_ms": {k: {"p50": round(float(np.percentile(v, 50)), 4), "p99": round(float(np.percentile(v, 99)), 4)}
                        for k, v in lat.items() if v},
         "tuning": tuning,
-        "roofline": {"bound": "hbm", "kernel": f"k_find<{tuning['find_group']},{bool(tuning['find_prefetch_b2'])}>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_find (autotuned per load, see tuning)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     del levels, q100, q50, fresh, rows, outs

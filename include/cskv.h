@@ -177,6 +177,8 @@ int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, u
  *  CSKV_TUNE_FIND_BLOCKS_PER_CU  grid of a program's merged find run: 0 (default) = one lane group
  *                              per key; k in 1..64 = a persistent grid of k 256-thread blocks per
  *                              compute unit striding over the run's keys
+ *  CSKV_TUNE_FIND_PAIRS        1 = cskv_find serves two keys per lane group with their loads
+ *                              interleaved, 0 = one key per group (default)
  * cskv_set_tuning returns CSKV_EINVAL for an unknown parameter or value; cskv_get_tuning returns
  * the current value, or -1.
  */
@@ -184,7 +186,8 @@ enum {
     CSKV_TUNE_FIND_GROUP = 1,
     CSKV_TUNE_ROUTE_GROUP = 2,
     CSKV_TUNE_FIND_PREFETCH_B2 = 3,
-    CSKV_TUNE_FIND_BLOCKS_PER_CU = 4
+    CSKV_TUNE_FIND_BLOCKS_PER_CU = 4,
+    CSKV_TUNE_FIND_PAIRS = 5
 };
 int cskv_set_tuning(cskv_table* table, int param, int value);
 int cskv_get_tuning(const cskv_table* table, int param);

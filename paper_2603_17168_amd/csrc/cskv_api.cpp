@@ -131,6 +131,7 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->route_group = 8;
     t->prefetch_b2 = 0;
     t->blocks_per_cu = 0;
+    t->find_pairs = 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         delete t;
@@ -178,7 +179,7 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
     if (!aligned(d_keys, 8) || !aligned(d_values_out, 16) || (d_scores_out && !aligned(d_scores_out, 8)))
         return CSKV_EINVAL;
     return hip_rc(launch_find(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
-                              table->prefetch_b2, as_stream(stream)));
+                              table->prefetch_b2, table->find_pairs, as_stream(stream)));
 }
 
 }  // extern "C"
@@ -290,6 +291,10 @@ int cskv_set_tuning(cskv_table* table, int param, int value) {
             if (value < 0 || value > 64) return CSKV_EINVAL;
             table->blocks_per_cu = value;
             return CSKV_OK;
+        case CSKV_TUNE_FIND_PAIRS:
+            if (value != 0 && value != 1) return CSKV_EINVAL;
+            table->find_pairs = value;
+            return CSKV_OK;
         default: return CSKV_EINVAL;
     }
 }
@@ -301,6 +306,7 @@ int cskv_get_tuning(const cskv_table* table, int param) {
         case CSKV_TUNE_ROUTE_GROUP: return table->route_group;
         case CSKV_TUNE_FIND_PREFETCH_B2: return table->prefetch_b2;
         case CSKV_TUNE_FIND_BLOCKS_PER_CU: return table->blocks_per_cu;
+        case CSKV_TUNE_FIND_PAIRS: return table->find_pairs;
         default: return -1;
     }
 }

@@ -127,7 +127,7 @@ size_t erase_ws_bytes(uint64_t n);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_clear_table(const TableView& t, hipStream_t s);
 hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
-                       uint64_t* scores_out, int group, int prefetch_b2, hipStream_t s);
+                       uint64_t* scores_out, int group, int prefetch_b2, int pairs, hipStream_t s);
 hipError_t launch_find_multi(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, int group,
                              int prefetch_b2, unsigned blocks, hipStream_t s);
 hipError_t launch_find_args(const TableView& t, const FindDescArgs& a, int group, int prefetch_b2, hipStream_t s);
@@ -162,6 +162,7 @@ struct cskv_table {
     int route_group;    // lanes per key of the upsert route kernel
     int prefetch_b2;    // find loads both candidate digest lines at once
     int blocks_per_cu;  // persistent grid of merged find runs: blocks per compute unit (0 = one group per key)
+    int find_pairs;     // find: two keys per lane group
     int num_cus;
 };
 

@@ -156,9 +156,11 @@ def test_lfu_zipf_like_duplicates():
     tw.check_table()
 
 
+@pytest.mark.parametrize("pairs", [0, 1])
 @pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 65, 257, 4099])
-def test_ragged_batch_sizes(n):
+def test_ragged_batch_sizes(n, pairs):
     tw = Twin(64 * 128, 12, "dual", "lru", seed=n)
+    tw.gpu.set_tuning(find_pairs=pairs)
     k = np_keys(50, n)
     tw.upsert(k, evict=True)
     tw.find(np.concatenate([k, np_keys(51, n)]))
@@ -172,6 +174,7 @@ def test_ragged_batch_sizes(n):
 def test_value_dims(dim):
     say(f"dim {dim}")
     tw = Twin(32 * 128, dim, "dual", "custom", seed=dim)
+    tw.gpu.set_tuning(find_pairs=dim % 8 == 0)
     rng = np.random.default_rng(dim)
     for rep in range(3):
         k = np_keys(60, 6000, rep * 2000)
@@ -201,9 +204,10 @@ def test_launch_shapes_do_not_change_results():
     """Every tuning variant (probe lanes per key, b2 prefetch, route lanes) gives bit-identical
     outputs and tables, and matches the oracle."""
     say("tuning variants")
-    for fg, pre, rg in [(4, 0, 8), (8, 1, 16), (16, 1, 4), (16, 0, 16)]:
+    for fg, pre, rg, pairs in [(4, 0, 8, 0), (8, 1, 16, 0), (16, 1, 4, 0), (16, 0, 16, 0), (4, 0, 8, 1),
+                               (8, 1, 8, 1), (16, 0, 4, 1)]:
         tw = Twin(64 * 128, 8, "dual", "lru", seed=9)
-        tw.gpu.set_tuning(find_group=fg, find_prefetch_b2=pre, route_group=rg)
+        tw.gpu.set_tuning(find_group=fg, find_prefetch_b2=pre, route_group=rg, find_pairs=pairs)
         got = tw.gpu.get_tuning()
         assert (got["find_group"], got["route_group"], got["find_prefetch_b2"]) == (fg, rg, pre)
         for rep in range(4):
