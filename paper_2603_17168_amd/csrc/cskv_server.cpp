@@ -9,6 +9,7 @@
 
 #include "../../include/cskv.h"
 #include "cskv_internal.h"
+#include "cskv_ring.h"
 
 using namespace cskv;
 
@@ -41,57 +42,6 @@ uint64_t footprint(const cskv_request& r, uint32_t dim) {
     if (r.op == CSKV_REQ_FIND) return r.n * 8 + r.n * row + r.n;
     return r.n * 8 + r.n * row + (r.d_scores ? r.n * 8 : 0) + r.n + r.n * (16 + row) + 8;
 }
-
-// ring allocator over the arena: requests complete in admission order, so frees come in order.
-// Nonzero allocations are laid out in order, wrapping to offset 0 when the end is reached; the
-// live bytes are [tail, head) before a wrap and [tail, size) + [0, head) after one, where tail
-// is the start of the oldest and head the end of the newest nonzero allocation.
-struct Ring {
-    uint8_t* base = nullptr;
-    size_t size = 0, head = 0, tail = 0, last = 0;  // last: start of the newest nonzero allocation
-    size_t nonzero = 0;
-    std::deque<std::pair<size_t, size_t>> live;  // (offset, bytes) in allocation order
-    bool alloc(size_t bytes, size_t* off) {
-        if (bytes > size) return false;
-        if (bytes == 0) {  // takes no space; keeps its place in the completion order
-            live.push_back({0, 0});
-            *off = 0;
-            return true;
-        }
-        size_t pos;
-        if (nonzero == 0) {
-            pos = 0;
-            tail = 0;
-        } else if (tail <= last) {  // not wrapped: free are [head, size) and [0, tail)
-            if (head + bytes <= size) pos = head;
-            else if (bytes <= tail) pos = 0;
-            else return false;
-        } else {  // wrapped: free is [head, tail)
-            if (head + bytes <= tail) pos = head;
-            else return false;
-        }
-        live.push_back({pos, bytes});
-        ++nonzero;
-        last = pos;
-        head = pos + bytes;
-        *off = pos;
-        return true;
-    }
-    void free_front() {
-        if (live.front().second) --nonzero;
-        live.pop_front();
-        if (nonzero == 0) {
-            head = tail = last = 0;
-            return;
-        }
-        for (const auto& e : live) {  // the oldest allocation that holds bytes
-            if (e.second) {
-                tail = e.first;
-                break;
-            }
-        }
-    }
-};
 
 double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -126,8 +76,8 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
     if (ws_bytes < ups_bytes + align256(cfg->arena_budget_bytes)) return CSKV_ENOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_ws);
-    Ring ring;
-    ring.base = ws + ups_bytes;
+    cskv::Ring ring;
+    uint8_t* const arena = ws + ups_bytes;
     ring.size = align256(cfg->arena_budget_bytes);
 
     cskv_serve_stats st{};
@@ -166,7 +116,7 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
                 break;
             }
             deferred_flag = false;
-            uint8_t* a = ring.base + off;
+            uint8_t* a = arena + off;
             if (r.op == CSKV_REQ_FIND) {
                 if (!r.d_values_out) {
                     r.d_values_out = reinterpret_cast<float*>(a);
