@@ -164,6 +164,29 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
     torch.cuda.synchronize()
     res["plain_s"] = time.perf_counter() - t0
     ref = outputs()
+
+    def build(overlap):
+        pr = cskv.Program(base, overlap=overlap)
+        for d in ops:
+            tuner.apply(base, tuning, d["n"])
+            if d["op"] == "find":
+                pr.add_find(d["keys"], d["out"], d["flag"])
+            elif d["op"] == "upsert":
+                pr.add_insert_or_assign(d["keys"], d["values"], None, d["flag"])
+            else:
+                pr.add_erase(d["keys"], d["flag"])
+        return pr.finalize()
+
+    same = True
+    serial = build(False)
+    restore()
+    t0 = time.perf_counter()
+    serial.launch()
+    torch.cuda.synchronize()
+    res["program_serial_s"] = time.perf_counter() - t0
+    same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
+                        for a, b in zip(ref, outputs()))
+    del serial
     prog = cskv.Program(base)
     for d in ops:
         tuner.apply(base, tuning, d["n"])
@@ -179,8 +202,8 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
     prog.launch()
     torch.cuda.synchronize()
     res["program_s"] = time.perf_counter() - t0
-    same = all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
-               for a, b in zip(ref, outputs()))
+    same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
+                        for a, b in zip(ref, outputs()))
     stream = torch.cuda.Stream(device=dev)
     prog.capture(stream)
     restore()
@@ -197,6 +220,7 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
                        f"2^{log2_cap} slots dim {dim} LRU at load {load}",
            "total_keys": total, "segments": prog.segments,
            "plain_bkvs": round(total / res["plain_s"] / 1e9, 3),
+           "program_serial_bkvs": round(total / res["program_serial_s"] / 1e9, 3),
            "program_bkvs": round(total / res["program_s"] / 1e9, 3),
            "graph_bkvs": round(total / res["graph_s"] / 1e9, 3),
            "graph_vs_plain": round(res["plain_s"] / res["graph_s"], 3),

@@ -229,6 +229,16 @@ int cskv_program_add_insert_and_evict(cskv_program* prog, uint64_t n, const uint
                                       uint64_t* d_ev_keys, float* d_ev_values, uint64_t* d_ev_scores,
                                       uint64_t* d_n_evicted);
 int cskv_program_add_erase(cskv_program* prog, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased);
+/*
+ * 1 (default): the program's phases are ordered by events instead of one stream: readers (find
+ * runs, the routing of an upsert, the probe of an erase) wait only for the last writer; writers
+ * (the apply of an upsert, the clear of an erase) wait for the last writer and every reader
+ * since; the scratch preparation of an upsert (clear, dedupe) waits only for the previous user of
+ * its scratch slot (two slots rotate).  Independent phases of different batches then overlap on
+ * the device.  0: every phase in program order on the launch stream.  Set before
+ * cskv_program_set_workspace.
+ */
+int cskv_program_set_overlap(cskv_program* prog, int enabled);
 size_t cskv_program_workspace_bytes(const cskv_program* prog);
 int cskv_program_set_workspace(cskv_program* prog, void* d_ws, size_t ws_bytes);
 /* number of kernel-sequence segments: merged find runs + upserts + erases */

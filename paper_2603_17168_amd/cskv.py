@@ -60,6 +60,7 @@ def lib():
         "cskv_program_add_insert_and_evict": (I, [P, U64, P, P, P, P, P, P, P, P]),
         "cskv_program_add_erase": (I, [P, U64, P, P]),
         "cskv_program_workspace_bytes": (SZ, [P]),
+        "cskv_program_set_overlap": (I, [P, I]),
         "cskv_program_set_workspace": (I, [P, P, SZ]),
         "cskv_program_segments": (U32, [P]),
         "cskv_program_launch": (I, [P, P]),
@@ -266,11 +267,12 @@ class Program:
     run; upserts and erases are serialization points; the whole program can be captured once as a
     hipGraph and replayed.  Tensors passed to add_* are kept alive by the program."""
 
-    def __init__(self, table: Table):
+    def __init__(self, table: Table, overlap: bool = True):
         self.table = table
         h = ctypes.c_void_p()
         _check(lib().cskv_program_create(ctypes.byref(h), table._h), "cskv_program_create")
         self._h = h
+        _check(lib().cskv_program_set_overlap(h, int(overlap)), "cskv_program_set_overlap")
         self._keep = []
         self._ws = None
 

@@ -186,7 +186,8 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
 
 namespace cskv {
 
-int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, UpsertWs* out,
+                size_t* zero_out) {
     const uint64_t n = a.n;
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
@@ -197,7 +198,7 @@ int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws
     const UpsertLayout L = upsert_layout(n, table->view.nbuckets);
     if (ws_bytes < L.total) return CSKV_ENOMEM;
     uint8_t* b = reinterpret_cast<uint8_t*>(d_ws);
-    UpsertWs w;
+    UpsertWs& w = *out;
     w.dd = reinterpret_cast<DedupeEntry*>(b + L.off_dd);
     w.okey = reinterpret_cast<uint64_t*>(b + L.off_okey);
     w.ctr = reinterpret_cast<uint32_t*>(b + L.off_ctr);
@@ -213,8 +214,16 @@ int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws
     w.logP = L.logP;
     w.cap = L.cap;
     w.list_mode = L.list_mode;
-    const size_t zero_bytes = table->policy == CSKV_SCORE_LFU ? L.off_zero_end_lfu : L.off_zero_end;
-    return hip_rc(launch_upsert(table->view, w, n, a.keys, a.vals, a.scores, a.status, a.ev, zero_bytes,
+    *zero_out = table->policy == CSKV_SCORE_LFU ? L.off_zero_end_lfu : L.off_zero_end;
+    return CSKV_OK;
+}
+
+int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    UpsertWs w;
+    size_t zero_bytes = 0;
+    const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes);
+    if (rc != CSKV_OK || a.n == 0) return rc;
+    return hip_rc(launch_upsert(table->view, w, a.n, a.keys, a.vals, a.scores, a.status, a.ev, zero_bytes,
                                 table->route_group, stream));
 }
 

@@ -136,6 +136,19 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
                          size_t zero_bytes, int group, hipStream_t s);
 hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                         uint32_t* ws_slot, int group, hipStream_t s);
+// the phases of an upsert / erase, for callers that order them with events (batched programs):
+// prep (scratch clear, dedupe) and route only read the table; apply writes it; finish writes the
+// statuses; an erase probe reads, its clear writes
+hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                              const uint64_t* scores, const EvictOut& ev, size_t zero_bytes, hipStream_t s);
+hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                               const uint64_t* scores, int group, hipStream_t s);
+hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals,
+                               const EvictOut& ev, hipStream_t s);
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s);
+hipError_t launch_erase_probe(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
+                              uint32_t* ws_slot, int group, hipStream_t s);
+hipError_t launch_erase_clear(const TableView& t, uint64_t n, uint32_t* ws_slot, hipStream_t s);
 hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s);
 hipError_t launch_export(const TableView& t, uint64_t b0, uint64_t b1, uint64_t* keys, float* vals,
                          uint64_t* scores, uint64_t* slots, uint64_t* count, hipStream_t s);
@@ -167,6 +180,8 @@ struct cskv_table {
 };
 
 namespace cskv {
+// validates an upsert and lays out its workspace (CSKV_* code)
+int plan_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, UpsertWs* w, size_t* zero_bytes);
 int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
 int enqueue_erase(cskv_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased, void* ws, size_t ws_bytes,
                   hipStream_t s);

@@ -323,8 +323,8 @@ __global__ void __launch_bounds__(256) k_erase_clear(TableView t, uint64_t n, co
     t.bmin[2 * (e / kSlots) + 1] = 0;  // the bucket is no longer full: its cached minimum is void
 }
 
-hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased, uint32_t* ws_slot,
-                        int group, hipStream_t s) {
+hipError_t launch_erase_probe(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased, uint32_t* ws_slot,
+                              int group, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const unsigned nb = blocks_for(n * group, 256);
     switch (group) {
@@ -332,8 +332,20 @@ hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, ui
         case 16: k_erase_probe<16><<<nb, 256, 0, s>>>(t, n, keys, erased, ws_slot); break;
         default: k_erase_probe<8><<<nb, 256, 0, s>>>(t, n, keys, erased, ws_slot); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_erase_clear(const TableView& t, uint64_t n, uint32_t* ws_slot, hipStream_t s) {
+    if (n == 0) return hipSuccess;
     k_erase_clear<<<blocks_for(n, 256), 256, 0, s>>>(t, n, ws_slot);
     return hipGetLastError();
+}
+
+hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased, uint32_t* ws_slot,
+                        int group, hipStream_t s) {
+    const hipError_t e = launch_erase_probe(t, n, keys, erased, ws_slot, group, s);
+    if (e != hipSuccess) return e;
+    return launch_erase_clear(t, n, ws_slot, s);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -655,25 +655,51 @@ static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, cons
     k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores);
 }
 
-hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
-                         const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
-                         hipStream_t s) {
+hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                              const uint64_t* scores, const EvictOut& ev, size_t zero_bytes, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipError_t e = launch_fill_zero(w.dd, zero_bytes, s);
     if (e != hipSuccess) return e;
     k_dedupe<<<blocks_for(n, 256), 256, 0, s>>>(t, w, n, keys, scores, ev.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                               const uint64_t* scores, int group, hipStream_t s) {
+    if (n == 0) return hipSuccess;
     switch (group) {
         case 4: launch_route<4>(t, w, n, keys, scores, s); break;
         case 16: launch_route<16>(t, w, n, keys, scores, s); break;
         default: launch_route<8>(t, w, n, keys, scores, s); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals, const EvictOut& ev,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
     const uint64_t visit = w.list_mode ? (n < t.nbuckets ? n : t.nbuckets) : t.nbuckets;
     k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
     uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
     if (slow_blocks > 2048) slow_blocks = 2048;
     k_apply_slow<<<(unsigned)slow_blocks, 64, 0, s>>>(t, w, vals, ev);
-    if (status) k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status);
     return hipGetLastError();
+}
+
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s) {
+    if (n == 0 || !status) return hipSuccess;
+    k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
+                         const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
+                         hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
+    if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
+    if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
+    return launch_upsert_finish(w, n, status, s);
 }
 
 }  // namespace cskv

@@ -37,8 +37,8 @@ def run_calls(t, ops):
             t.erase(d["keys"], erased_out=d["flag"])
 
 
-def build_program(t, ops, tuning=None):
-    p = cskv.Program(t)
+def build_program(t, ops, tuning=None, overlap=True):
+    p = cskv.Program(t, overlap=overlap)
     for d in ops:
         if tuning:
             autotune.apply(t, tuning, d["n"])
@@ -112,7 +112,8 @@ def test_program_segments_merge_reader_runs():
         p.add_find(k, v, f)  # closed after finalize
 
 
-def test_program_matches_calls_and_oracle():
+@pytest.mark.parametrize("overlap", [True, False])
+def test_program_matches_calls_and_oracle(overlap):
     """48 uneven batches (16..4096 keys, 70/25/5 find/upsert/erase) on a 2^15-slot table: the
     eager calls are checked against the oracle call by call; the program launched eagerly and
     the captured graph replayed must give the same outputs and the same table."""
@@ -148,13 +149,13 @@ def test_program_matches_calls_and_oracle():
     assert base.clock == ora.clock
     # the same schedule as one program, and as a captured graph
     ops_p = fresh_outputs(ops)
-    prog = build_program(t_prog, ops_p)
+    prog = build_program(t_prog, ops_p, overlap=overlap)
     prog.launch()
     torch.cuda.synchronize()
     same_outputs(ops, ops_p)
     same_tables(base, t_prog)
     ops_g = fresh_outputs(ops)
-    prog_g = build_program(t_graph, ops_g)
+    prog_g = build_program(t_graph, ops_g, overlap=overlap)
     s = torch.cuda.Stream()
     prog_g.capture(s)
     prog_g.replay(s)
@@ -164,7 +165,8 @@ def test_program_matches_calls_and_oracle():
     assert t_graph.clock == ora.clock
 
 
-def test_graph_replays_are_repeatable():
+@pytest.mark.parametrize("overlap", [True, False])
+def test_graph_replays_are_repeatable(overlap):
     """Replay a captured program several times from the same starting table (restored eagerly
     between replays): every replay must reproduce the eager program's outputs and table."""
     cap, dim = 1 << 15, 8
@@ -176,7 +178,7 @@ def test_graph_replays_are_repeatable():
     run_calls(ref, ops)
     snap = base.storage.clone()
     ops_g = fresh_outputs(ops)
-    prog = build_program(base, ops_g)
+    prog = build_program(base, ops_g, overlap=overlap)
     s = torch.cuda.Stream()
     prog.capture(s)
     for rep in range(3):

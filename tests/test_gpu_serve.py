@@ -65,10 +65,10 @@ def test_serving_alone_equals_mix_and_oracle(mode):
     nreq = 160
     ops, sizes, keys, vals, arr = make_trace(base, nreq, seed=11, qps=20000.0)
     tr = serve.Trace(base, ops, sizes, keys, vals, arr, with_results=True)
-    budget = 4 << 20 if mode == "tight_budget" else 256 << 20
+    budget = 1 << 20 if mode == "tight_budget" else 256 << 20
     say(f"serving {nreq} requests, mode {mode}")
     stats, times = serve.serve(base, tr, budget_bytes=budget, max_inflight_groups=2, max_merge=16,
-                               realtime=(mode != "burst"))
+                               realtime=(mode == "realtime"))
     say(stats)
     assert stats["completed"] == nreq
     assert np.array_equal(times["seq"], np.arange(nreq))  # admission order = arrival order
