@@ -207,7 +207,8 @@ int cskv_set_clock(cskv_table* table, uint64_t clock);
  *  - consecutive finds form a reader run (readers never conflict, Sec. 3.5 triple-group matrix)
  *    and execute as ONE merged kernel over all their keys (a persistent grid when
  *    CSKV_TUNE_FIND_BLOCKS_PER_CU > 0), with the table's tuning at the time the run's first
- *    find was added;
+ *    find was added; a find whose buffers overlap an output of a find already in the run
+ *    starts a new run;
  *  - every upsert or erase is a serialization point (inserter group) run as its usual kernels.
  * All pointers are recorded at add time and must stay valid (and unchanged in size) while the
  * program is launched or replayed.  The program needs a device workspace of
@@ -230,19 +231,29 @@ int cskv_program_add_insert_and_evict(cskv_program* prog, uint64_t n, const uint
                                       uint64_t* d_n_evicted);
 int cskv_program_add_erase(cskv_program* prog, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased);
 /*
- * 1 (default): the program's phases are ordered by events instead of one stream: readers (find
- * runs, the routing of an upsert, the probe of an erase) wait only for the last writer; writers
- * (the apply of an upsert, the clear of an erase) wait for the last writer and every reader
- * since; the scratch preparation of an upsert (clear, dedupe) waits only for the previous user of
- * its scratch slot (two slots rotate).  Independent phases of different batches then overlap on
- * the device.  0: every phase in program order on the launch stream.  Set before
- * cskv_program_set_workspace.
+ * 1: the program is a graph of phases instead of one kernel sequence.  Phases: a find
+ * run; the probe and the clear of an erase; the scratch preparation (clear, dedupe), routing,
+ * apply and status gather of an upsert.  Readers (find runs, routings, probes) wait only for the
+ * last writer; writers (applies, clears) wait for the last writer and every reader since (the
+ * reader/writer rule of Sec. 3.5); the first phase of an upsert or erase waits only for the
+ * previous user of its scratch slot (two slots rotate).  An op whose buffers (keys, values,
+ * scores, outputs) overlap a buffer of an earlier op that one of the two writes starts after that
+ * op is complete, and such a find is not merged into the earlier find's run, so results equal
+ * those of the calls issued one by one whatever the aliasing.  cskv_program_launch runs the
+ * phases on the program's own default-priority streams ordered by events, forked from and joined
+ * back into the launch stream; cskv_program_capture builds a hipGraph with one child node per
+ * phase (each recorded alone on `stream`) and the dependencies as edges.  Independent phases of
+ * different batches then overlap on the device, at the price of cross-stream event waits.
+ * 0 (default): every phase in program order on the launch stream (the captured graph is that one
+ * sequence).  Set before cskv_program_set_workspace.
  */
 int cskv_program_set_overlap(cskv_program* prog, int enabled);
 size_t cskv_program_workspace_bytes(const cskv_program* prog);
 int cskv_program_set_workspace(cskv_program* prog, void* d_ws, size_t ws_bytes);
 /* number of kernel-sequence segments: merged find runs + upserts + erases */
 uint32_t cskv_program_segments(const cskv_program* prog);
+/* number of phases of the overlapped form (0 when overlap is off or before set_workspace) */
+uint32_t cskv_program_phases(const cskv_program* prog);
 int cskv_program_launch(cskv_program* prog, void* stream);
 int cskv_program_capture(cskv_program* prog, void* stream);
 int cskv_program_replay(cskv_program* prog, void* stream);

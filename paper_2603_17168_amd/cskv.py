@@ -63,6 +63,7 @@ def lib():
         "cskv_program_set_overlap": (I, [P, I]),
         "cskv_program_set_workspace": (I, [P, P, SZ]),
         "cskv_program_segments": (U32, [P]),
+        "cskv_program_phases": (U32, [P]),
         "cskv_program_launch": (I, [P, P]),
         "cskv_program_capture": (I, [P, P]),
         "cskv_program_replay": (I, [P, P]),
@@ -267,7 +268,7 @@ class Program:
     run; upserts and erases are serialization points; the whole program can be captured once as a
     hipGraph and replayed.  Tensors passed to add_* are kept alive by the program."""
 
-    def __init__(self, table: Table, overlap: bool = True):
+    def __init__(self, table: Table, overlap: bool = False):
         self.table = table
         h = ctypes.c_void_p()
         _check(lib().cskv_program_create(ctypes.byref(h), table._h), "cskv_program_create")
@@ -332,6 +333,10 @@ class Program:
     @property
     def segments(self) -> int:
         return int(lib().cskv_program_segments(self._h))
+
+    @property
+    def phases(self) -> int:
+        return int(lib().cskv_program_phases(self._h))
 
     def _s(self, stream):
         s = stream if stream is not None else torch.cuda.current_stream(self.table.device)

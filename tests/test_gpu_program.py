@@ -95,21 +95,82 @@ def prefilled(capacity, dim, n_prefill, stream=1):
 def test_program_segments_merge_reader_runs():
     t = cskv.Table(128 * 64, 8, "dual", "lru")
     k = gen_keys(5, 100, device="cuda")
-    v = torch.zeros((100, 8), dtype=torch.float32, device="cuda")
-    f = torch.empty(100, dtype=torch.uint8, device="cuda")
-    p = cskv.Program(t)
-    p.add_find(k, v, f)
-    p.add_find(k, v, f)
-    p.add_insert_or_assign(k, v)
-    p.add_find(k, v, f)
+    v = [torch.zeros((100, 8), dtype=torch.float32, device="cuda") for _ in range(6)]
+    f = [torch.empty(100, dtype=torch.uint8, device="cuda") for _ in range(6)]
+    p = cskv.Program(t, overlap=True)
+    p.add_find(k, v[0], f[0])
+    p.add_find(k, v[1], f[1])
+    p.add_insert_or_assign(k, v[5])
+    p.add_find(k, v[2], f[2])
     p.add_erase(k)
-    p.add_find(k, v, f)
-    p.add_find(k, v, f)
-    p.add_find(k[:0], v[:0], f[:0])  # empty batches vanish
+    p.add_find(k, v[3], f[3])
+    p.add_find(k, v[4], f[4])
+    p.add_find(k[:0], v[0][:0], f[0][:0])  # empty batches vanish
     p.finalize()
     assert p.segments == 5
+    # find run, upsert (prep, route, apply: no status), find run, erase (probe, clear), find run
+    assert p.phases == 8
     with pytest.raises(cskv.CskvError):
-        p.add_find(k, v, f)  # closed after finalize
+        p.add_find(k, v[0], f[0])  # closed after finalize
+
+
+@pytest.mark.parametrize("overlap", [True, False])
+def test_program_aliasing_buffers_keep_call_order(overlap):
+    """Ops that share buffers: two finds into the same outputs split the reader run (the second
+    one's results remain); a find's output rows are the values of a later upsert (read after
+    write); an erase whose flags reuse an upsert's status buffer (write after write).  Eager
+    launch and graph replay both equal the calls issued one by one."""
+    cap, dim = 1 << 14, 8
+    base = prefilled(cap, dim, 9000)
+    a = gen_keys(1, 3000, 0, device="cuda")      # resident
+    b = gen_keys(1, 3000, 3000, device="cuda")   # resident, other rows
+    fresh = gen_keys(60, 3000, device="cuda")
+    out = torch.zeros((3000, dim), dtype=torch.float32, device="cuda")
+    fl = torch.empty(3000, dtype=torch.uint8, device="cuda")
+    st = torch.empty(3000, dtype=torch.uint8, device="cuda")
+
+    def run(t, prog=None):
+        out.fill_(-7.0)
+        fl.fill_(9)
+        st.fill_(9)
+        torch.cuda.synchronize()
+        if prog is None:
+            t.find(a, values_out=out, found_out=fl, want_scores=False)
+            t.find(b, values_out=out, found_out=fl, want_scores=False)
+            t.insert_or_assign(fresh, out, status_out=st)
+            t.erase(b, erased_out=st)
+        else:
+            prog()
+        torch.cuda.synchronize()
+        return out.clone(), fl.clone(), st.clone()
+
+    ref_t = clone(base)
+    ref = run(ref_t)
+    assert bool((ref[1] == 1).all()) and bool((ref[2] <= 1).all())  # st ends as the erase's flags
+
+    def make(t):
+        p = cskv.Program(t, overlap=overlap)
+        p.add_find(a, out, fl)
+        p.add_find(b, out, fl)
+        p.add_insert_or_assign(fresh, out, None, st)
+        p.add_erase(b, st)
+        return p.finalize()
+
+    t1 = clone(base)
+    p1 = make(t1)
+    assert p1.segments == 4
+    got = run(t1, p1.launch)
+    for x, y in zip(ref, got):
+        assert torch.equal(bits(x) if x.dtype == torch.float32 else x, bits(y) if y.dtype == torch.float32 else y)
+    same_tables(ref_t, t1)
+    t2 = clone(base)
+    p2 = make(t2)
+    s = torch.cuda.Stream()
+    p2.capture(s)
+    got = run(t2, lambda: (p2.replay(s), s.synchronize()))
+    for x, y in zip(ref, got):
+        assert torch.equal(bits(x) if x.dtype == torch.float32 else x, bits(y) if y.dtype == torch.float32 else y)
+    same_tables(ref_t, t2)
 
 
 @pytest.mark.parametrize("overlap", [True, False])
