@@ -294,6 +294,52 @@ def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
                       f"2^{int(np.log2(batch))} keys; {tot_s:.1f} s timed"}
 
 
+def counter_probe(dev, cap, dim, batch, loads):
+    """A short fixed sequence for hardware-counter runs (rocprofv3 --pmc): a 1 GiB device copy
+    (the scale reference for FETCH_SIZE / WRITE_SIZE), then per load factor on the C2 table: two
+    finds at 100 % hit, two at 50 % hit, two insert_or_assign of fresh keys and their erases.
+    Prints one JSON line naming the sequence of calls."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    seq = ["copy_1GiB"]
+    dst.copy_(src)
+    del src, dst
+    t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
+    t.set_tuning(find_group=8, find_prefetch_b2=0, find_pairs=1, route_group=8)  # the shapes the bench picks
+    rows = value_rows(12, gen_keys(600, batch, 0, device=dev), dim)
+    outs = torch.empty((batch, dim), dtype=torch.float32, device=dev)
+    found = torch.empty(batch, dtype=torch.uint8, device=dev)
+    status = torch.empty(batch, dtype=torch.uint8, device=dev)
+    erased = torch.empty(batch, dtype=torch.uint8, device=dev)
+    offered = 0
+    for li, lam in enumerate(loads):
+        offered, size = fill(t, lam, batch, dim, 1, offered, dev)
+        k, _, _, _ = t.export(with_values=False)
+        q100 = k[randint(100 + li, batch, k.numel(), device=dev)]
+        miss = gen_keys(900, batch // 2, li * batch, device=dev)
+        q50 = torch.cat([k[randint(200 + li, batch // 2, k.numel(), device=dev)], miss])
+        q50 = q50[torch.argsort(randint(300 + li, batch, 1 << 40, device=dev))]
+        del k
+        torch.cuda.synchronize()
+        for r in range(2):
+            t.find(q100, values_out=outs, found_out=found, want_scores=False)
+            seq.append(f"find100@{lam}")
+        for r in range(2):
+            t.find(q50, values_out=outs, found_out=found, want_scores=False)
+            seq.append(f"find50@{lam}")
+        for r in range(2):
+            fk = gen_keys(500 + li, batch, r * batch, device=dev)
+            t.insert_or_assign(fk, rows, status_out=status)
+            seq.append(f"upsert@{lam}")
+            if lam < 1.0:
+                t.erase(fk, erased_out=erased)
+                seq.append(f"erase@{lam}")
+        torch.cuda.synchronize()
+        log(f"probe: load {size / cap:.4f} done")
+    print(json.dumps({"counter_probe": seq, "capacity": cap, "dim": dim, "batch": batch}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +353,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="run only the short fixed call sequence used for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
@@ -319,6 +367,9 @@ def main():
     dim = args.dim
     batch = 1 << args.log2_batch
     loads = [float(x) for x in args.loads.split(",")]
+    if args.counter_probe:
+        counter_probe(dev, cap, dim, batch, loads)
+        return
 
     # ---------------- setup (untimed): tables at each load factor, query sets
     base = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
