@@ -40,6 +40,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the find kernel, bytes per key, from two rocprofv3 --pmc runs of
+# `bench.py --counter-probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter read
+# for a 1 GiB device copy in the same run; recorded for the find source with this SHA-256
+# (cskv_find.hip + cskv_device.h) and reported only while that source is unchanged.
+FIND_TRAFFIC = {"source_sha256": "134aebfdbd598ea859a727c248ad819eb0011f03c32f14a45ec7d2fd0c591859", "dim": 32,
+                "per_key": {"0.50": {"hit100": 602.7, "hit50": 460.8}, "0.75": {"hit100": 625.5, "hit50": 487.8},
+                            "0.90": {"hit100": 639.6, "hit50": 504.8}, "1.00": {"hit100": 650.1, "hit50": 516.2}}}
+
+
+def find_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cskv_find.hip", "cskv_device.h"):
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_17168_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def find_traffic_per_launch(dim: int, loads, batch: int):
+    """Mean measured HBM bytes per find launch over the bench's find launches (100 % and 50 % hit
+    at every load), or None when the counters do not cover them or the find source changed."""
+    if FIND_TRAFFIC["source_sha256"] != find_source_sha256() or FIND_TRAFFIC["dim"] != dim:
+        return None
+    tot = []
+    for lam in loads:
+        rec = FIND_TRAFFIC["per_key"].get(f"{lam:.2f}")
+        if rec is None:
+            return None
+        tot += [rec["hit100"] * batch, rec["hit50"] * batch]
+    return float(np.mean(tot))
+
+
 def find_bytes_per_key(dim: int, hit: bool, load: float) -> float:
     """Algorithmic bytes of one find (dual mode), counting every hit as a b1 hit (a lower bound):
     hit  = key + digest line + key granule + row read + row write + flag
@@ -48,6 +80,18 @@ def find_bytes_per_key(dim: int, hit: bool, load: float) -> float:
     if hit:
         return K_B + L_B + S_B + 2 * V + F_B
     return K_B + 2 * L_B + load * 0.5 * S_B + F_B
+
+
+def upsert_bytes_per_key(dim: int, load: float, batch: int, nbuckets: int) -> float:
+    """Algorithmic bytes of one insert_or_assign of a fresh key (dual mode): the input key and row,
+    both candidate digest lines (routing needs both occupancies), the digest byte, key and score
+    of the new entry, its row, the status.  In a full table (load 1) every insert replaces the
+    bucket's minimum, which takes the bucket's score line (8 lines) once per bucket per call."""
+    V = 4 * dim
+    b = K_B + V + 2 * L_B + (1 + 8 + 8) + V + F_B
+    if load >= 1.0:
+        b += 8 * L_B * min(1.0, nbuckets / batch)
+    return b
 
 
 class Level:
@@ -473,6 +517,12 @@ def main():
         find_bytes += [batch * find_bytes_per_key(dim, True, lam)] * len(f100)
         find_bytes += [batch * 0.5 * (find_bytes_per_key(dim, True, lam) + find_bytes_per_key(dim, False, lam))] * len(f50)
     achieved = float(np.sum(find_bytes) / (np.sum(find_ms) / 1e3) / 1e9)
+    ups_ms, ups_bytes = [], []
+    for li, lv in enumerate(levels):
+        ms = [x.elapsed_time(y) for x, y in zip(ev[f"f50_{li}_b"], ev[f"ups_{li}_b"])]
+        ups_ms += ms
+        ups_bytes += [batch * upsert_bytes_per_key(dim, lv.target, batch, cap // 128)] * len(ms)
+    ups_achieved = float(np.sum(ups_bytes) / (np.sum(ups_ms) / 1e3) / 1e9)
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -495,7 +545,11 @@ def main():
                        for k, v in lat.items() if v},
         "tuning": tuning,
         "roofline": {"bound": "hbm", "kernel": "k_find (autotuned per load, see tuning)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": find_traffic_per_launch(dim, [lv.target for lv in levels], batch)},
+        "roofline_upsert": {"bound": "hbm", "kernel": "insert_or_assign (route + apply kernels of one call)",
+                            "achieved": round(ups_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(ups_achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     del levels, q100, q50, fresh, rows, outs
     torch.cuda.synchronize()

@@ -156,6 +156,7 @@ __device__ __forceinline__ int nth_bit128(uint64_t lo, uint64_t hi, int r) {
 }
 
 constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
+constexpr int kSpecEntries = 4;   // list entries loaded before the bucket's count is known
 
 __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev,
                                                     uint8_t* __restrict__ status) {
@@ -168,8 +169,18 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
     if (w.list_mode) bb = bb < w.ctr[kCtrTouched] ? w.touched[bb] : t.nbuckets;
     const uint32_t b = (uint32_t)bb;
+    // the count, the first inline entries (one 128-byte line) and the digest line do not depend
+    // on one another: all three loads are issued before the first is needed (entries past the
+    // count are never used; later entries are loaded once the count is known)
     uint32_t m = 0;
-    if (bb < t.nbuckets) m = t.cnt[b];
+    Entry spec{0, 0, 0, kInsertSlot};
+    uint2 dv = make_uint2(0u, 0u);
+    const uint32_t nspec = w.cap < (uint32_t)kSpecEntries ? w.cap : (uint32_t)kSpecEntries;
+    if (bb < t.nbuckets) {
+        m = t.cnt[b];
+        if ((uint32_t)lane < nspec) spec = load_entry(w.il + (size_t)b * w.cap + lane);
+        dv = *reinterpret_cast<const uint2*>(t.dig + (size_t)b * kSlots + lane * SPL);
+    }
     if (m > (uint32_t)kFastMax) {  // crowded: register the bucket, its cl region and its work units
         if (lane == 0) {
             const uint32_t k = atomicAdd(w.ctr + kCtrSlow, 1u);
@@ -201,7 +212,7 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
 
     if (m > 0) {
         has = lane < (int)m;
-        if (has) e = fetch_entry(w, b, (uint32_t)lane);
+        if (has) e = (uint32_t)lane < nspec ? spec : fetch_entry(w, b, (uint32_t)lane);
         // every occurrence of a key is in this list: the last one (largest input position) stands
         // for the key (LWW); LFU increments of all occurrences are summed, saturating
         const uint32_t pos = (uint32_t)e.w;
@@ -229,7 +240,6 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
         }
         is_upd = rep && e.slot != kInsertSlot;
         is_ins = rep && e.slot == kInsertSlot;
-        const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
         const uint32_t emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
         const int occ = kSlots - gsum_i<GA>(__popc(emask8));
         const int nfree = kSlots - occ;
@@ -364,34 +374,63 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             }
         }
     }
-    // rows: chunk c of every row by lane c mod 16; updates before evictions
+    // rows: chunk c of every row by lane c mod 16; updates before evictions.  Two rows at a time,
+    // both loads before both stores (the two slots differ: updates hit distinct slots, inserts
+    // distinct new slots, each of which is its own victim's slot)
     const uint32_t chunks = t.dim >> 2;
-    for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
-        const int x = __ffs(ub) - 1;
-        const int us = __shfl((int)e.slot, x, GA);
-        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
-        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
-        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
-        for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+    for (uint32_t ub = upd_bits; ub;) {
+        const int x0 = __ffs(ub) - 1;
+        ub &= ub - 1;
+        const bool two = ub != 0;
+        const int x1 = two ? __ffs(ub) - 1 : x0;
+        if (two) ub &= ub - 1;
+        const int us0 = __shfl((int)e.slot, x0, GA), us1 = __shfl((int)e.slot, x1, GA);
+        const uint32_t p0 = (uint32_t)__shfl((int)(uint32_t)e.w, x0, GA);
+        const uint32_t p1 = (uint32_t)__shfl((int)(uint32_t)e.w, x1, GA);
+        uint4* d0 = reinterpret_cast<uint4*>(t.vals + (eb + us0) * t.dim);
+        uint4* d1 = reinterpret_cast<uint4*>(t.vals + (eb + us1) * t.dim);
+        const uint4* s0 = reinterpret_cast<const uint4*>(vals + (size_t)p0 * t.dim);
+        const uint4* s1 = reinterpret_cast<const uint4*>(vals + (size_t)p1 * t.dim);
+        for (uint32_t c = lane; c < chunks; c += GA) {
+            const uint4 a0 = s0[c];
+            const uint4 a1 = two ? s1[c] : a0;
+            d0[c] = a0;
+            if (two) d1[c] = a1;
+        }
     }
+    uint32_t placed = 0;  // inserts that took a slot
     for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
         const int x = __ffs(ib) - 1;
-        const int ns = __shfl(new_slot, x, GA);
-        if (ns < 0) continue;
-        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
-        const bool xe = __shfl((int)evicts, x, GA) != 0;
-        const int xi = __shfl(evi, x, GA);
-        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + ns) * t.dim);
-        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
-        if (xe && ev.vals) {
-            uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
-            for (uint32_t c = lane; c < chunks; c += GA) {
-                const uint4 old = dst[c];
-                out[c] = old;
-                dst[c] = src[c];
-            }
-        } else {
-            for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+        if (__shfl(new_slot, x, GA) >= 0) placed |= 1u << x;
+    }
+    for (uint32_t ib = placed; ib;) {
+        const int x0 = __ffs(ib) - 1;
+        ib &= ib - 1;
+        const bool two = ib != 0;
+        const int x1 = two ? __ffs(ib) - 1 : x0;
+        if (two) ib &= ib - 1;
+        const int n0 = __shfl(new_slot, x0, GA), n1 = __shfl(new_slot, x1, GA);
+        const uint32_t p0 = (uint32_t)__shfl((int)(uint32_t)e.w, x0, GA);
+        const uint32_t p1 = (uint32_t)__shfl((int)(uint32_t)e.w, x1, GA);
+        const bool v0 = ev.vals && __shfl((int)evicts, x0, GA) != 0;
+        const bool v1 = two && ev.vals && __shfl((int)evicts, x1, GA) != 0;
+        const int i0 = __shfl(evi, x0, GA), i1 = __shfl(evi, x1, GA);
+        uint4* d0 = reinterpret_cast<uint4*>(t.vals + (eb + n0) * t.dim);
+        uint4* d1 = reinterpret_cast<uint4*>(t.vals + (eb + n1) * t.dim);
+        const uint4* s0 = reinterpret_cast<const uint4*>(vals + (size_t)p0 * t.dim);
+        const uint4* s1 = reinterpret_cast<const uint4*>(vals + (size_t)p1 * t.dim);
+        uint4* o0 = reinterpret_cast<uint4*>(ev.vals + (ev_base + i0) * t.dim);
+        uint4* o1 = reinterpret_cast<uint4*>(ev.vals + (ev_base + i1) * t.dim);
+        for (uint32_t c = lane; c < chunks; c += GA) {
+            const uint4 a0 = s0[c];
+            const uint4 a1 = two ? s1[c] : a0;
+            uint4 q0 = a0, q1 = a0;
+            if (v0) q0 = d0[c];  // evicted rows are copied out before they are overwritten
+            if (v1) q1 = d1[c];
+            if (v0) o0[c] = q0;
+            if (v1) o1[c] = q1;
+            d0[c] = a0;
+            if (two) d1[c] = a1;
         }
     }
     // cached minimum of a full bucket (exact; every slot is occupied now).  Keys are read back
@@ -756,10 +795,10 @@ hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n
     // units the fast kernel registered
     const uint64_t nslow = n < t.nbuckets ? n : t.nbuckets;
     const uint64_t units = nslow + n / kSlowUnit + 1;
-    const unsigned ublocks = (unsigned)((units + 3) / 4 < 1024 ? (units + 3) / 4 : 1024);
+    const unsigned ublocks = (unsigned)((units + 3) / 4 < 256 ? (units + 3) / 4 : 256);
     k_slow_dedupe<<<ublocks, 256, 0, s>>>(t, w);
     k_slow_compact<<<ublocks, 256, 0, s>>>(t, w);
-    const unsigned slow_blocks = (unsigned)(nslow < 2048 ? nslow : 2048);
+    const unsigned slow_blocks = (unsigned)(nslow < 1024 ? nslow : 1024);
     k_apply_slow<<<slow_blocks, 64, 0, s>>>(t, w, vals, ev);
     if (status) k_slow_status<<<ublocks, 256, 0, s>>>(w, status);
     return hipGetLastError();
