@@ -72,14 +72,62 @@ def find_traffic_per_launch(dim: int, loads, batch: int):
     return float(np.mean(tot))
 
 
-def find_bytes_per_key(dim: int, hit: bool, load: float) -> float:
-    """Algorithmic bytes of one find (dual mode), counting every hit as a b1 hit (a lower bound):
-    hit  = key + digest line + key granule + row read + row write + flag
-    miss = key + two digest lines + expected false-positive key granules + flag."""
+def find_bytes_per_key(dim: int, hit_rate: float, load: float, frac_b2: float) -> float:
+    """Algorithmic bytes of one find (dual mode), the hot-path contract's model:
+    hit in b1 = key + digest line + key granule + row read + row write + flag;
+    hit in b2 = hit in b1 + the b2 digest line + the expected false-positive key granules of b1
+                (0.5 * load per line);
+    miss      = key + both digest lines + flag + expected false-positive key granules (load).
+    `frac_b2` is the measured share of the queried resident keys stored in their b2 bucket."""
     V = 4 * dim
-    if hit:
-        return K_B + L_B + S_B + 2 * V + F_B
-    return K_B + 2 * L_B + load * 0.5 * S_B + F_B
+    hit_b1 = K_B + L_B + S_B + 2 * V + F_B
+    hit_b2 = hit_b1 + L_B + 0.5 * load * S_B
+    miss = K_B + 2 * L_B + F_B + load * S_B
+    hit = (1.0 - frac_b2) * hit_b1 + frac_b2 * hit_b2
+    return hit_rate * hit + (1.0 - hit_rate) * miss
+
+
+_FM1, _FM2 = 0xFF51AFD7ED558CCD, 0xC4CEB9FE1A85EC53
+
+
+def _s64(x: int) -> int:
+    x &= (1 << 64) - 1
+    return x - (1 << 64) if x >> 63 else x
+
+
+def bucket_b1(keys: torch.Tensor, nbuckets: int) -> torch.Tensor:
+    """b1 of each key: MurmurHash3's 64-bit finalizer masked to the bucket count (int64 tensors
+    carry the u64 bits; right shifts are made logical with a mask)."""
+    def lsr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+    z = keys.to(torch.int64)
+    z = (z ^ lsr(z, 33)) * _s64(_FM1)
+    z = (z ^ lsr(z, 33)) * _s64(_FM2)
+    z = z ^ lsr(z, 33)
+    return z & (nbuckets - 1)
+
+
+def share_in_b2(keys: torch.Tensor, slots: torch.Tensor, nbuckets: int) -> float:
+    """Share of resident keys stored in their second-choice bucket."""
+    return float(((slots // 128) != bucket_b1(keys, nbuckets)).double().mean().item()) if keys.numel() else 0.0
+
+
+def copy_peak_gbs(dev, gib: int = 4, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth (bytes read + written per second), median of `reps`."""
+    a = torch.empty(gib << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / (float(np.median(ms)) / 1e3) / 1e9
 
 
 def upsert_bytes_per_key(dim: int, load: float, batch: int, nbuckets: int) -> float:
@@ -95,10 +143,11 @@ def upsert_bytes_per_key(dim: int, load: float, batch: int, nbuckets: int) -> fl
 
 
 class Level:
-    def __init__(self, table, load, resident_keys):
+    def __init__(self, table, load, resident_keys, frac_b2=0.0):
         self.t = table
         self.target = load
         self.resident = resident_keys
+        self.frac_b2 = frac_b2
 
 
 def fill(t: cskv.Table, target: float, batch: int, dim: int, key_stream: int, start: int, dev):
@@ -422,9 +471,11 @@ def main():
     for lam in loads:
         offered, size = fill(base, lam, batch, dim, 1, offered, dev)
         t = clone(base)
-        k, _, _, _ = t.export(with_values=False)
-        levels.append(Level(t, lam, k))
-        log(f"setup: load {lam:.2f} -> size {size} ({size / cap:.4f}), offered {offered}")
+        k, _, _, sl = t.export(with_values=False)
+        fb2 = share_in_b2(k, sl, cap // 128)
+        del sl
+        levels.append(Level(t, lam, k, fb2))
+        log(f"setup: load {lam:.2f} -> size {size} ({size / cap:.4f}), offered {offered}, in b2 {fb2:.3f}")
     del base
     torch.cuda.synchronize()
 
@@ -495,6 +546,20 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    # cold finds (untimed for `value`): a 512 MiB scrub write evicts the 256 MiB last-level cache
+    # before one 100 %-hit find per load
+    cold = {}
+    scrub = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    for li, lv in enumerate(levels):
+        scrub.fill_(li + 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lv.t.find(q100[li], values_out=outs, found_out=found, want_scores=False)
+        e1.record()
+        torch.cuda.synchronize()
+        cold[li] = batch / e0.elapsed_time(e1) / 1e6
+    del scrub
+
     kv_per_step = len(levels) * 3 * batch
     value = kv_per_step * args.steps / wall / 1e9
     per_op = {}
@@ -514,8 +579,10 @@ def main():
         lat["find"] += f100 + f50
         lat["upsert"] += ups
         find_ms += f100 + f50
-        find_bytes += [batch * find_bytes_per_key(dim, True, lam)] * len(f100)
-        find_bytes += [batch * 0.5 * (find_bytes_per_key(dim, True, lam) + find_bytes_per_key(dim, False, lam))] * len(f50)
+        find_bytes += [batch * find_bytes_per_key(dim, 1.0, lam, lv.frac_b2)] * len(f100)
+        find_bytes += [batch * find_bytes_per_key(dim, 0.5, lam, lv.frac_b2)] * len(f50)
+        per_op[f"{lv.target:.2f}"]["share_in_b2"] = round(lv.frac_b2, 4)
+        per_op[f"{lv.target:.2f}"]["find_hit100_cold_bkvs"] = round(cold[li], 3)
     achieved = float(np.sum(find_bytes) / (np.sum(find_ms) / 1e3) / 1e9)
     ups_ms, ups_bytes = [], []
     for li, lv in enumerate(levels):
@@ -554,6 +621,10 @@ def main():
     del levels, q100, q50, fresh, rows, outs
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    copy_peak = copy_peak_gbs(dev)
+    for k in ("roofline", "roofline_upsert"):
+        out[k]["copy_peak"] = round(copy_peak, 1)
+        out[k]["frac_of_copy_peak"] = round(out[k]["achieved"] / copy_peak, 4)
     if not args.no_batched:
         log("batched programs")
         out["batched"] = bench_batched(dev)
