@@ -47,7 +47,6 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.cap = inline_capacity(n, nb);
     const uint64_t nl = nb * L.cap;
     const uint64_t nslow = n < nb ? n : nb;
-    const uint64_t nunits = nslow + n / kSlowUnit + 1;
     size_t o = 0;
     // zeroed on every call: dedupe set, overflow keys, counters (and the LFU sums)
     L.off_dd = o;      o = align256(o + P * sizeof(DedupeEntry));
@@ -58,16 +57,11 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.off_sat = o;     o = align256(o + P * 4);
     L.off_zero_end_lfu = o;
     L.off_sstat = o;   o = align256(o + P);
+    L.off_slot_of = o; o = align256(o + n * 4);
     L.off_il = o;      o = align256(o + nl * sizeof(OpEntry));
     L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
     L.off_touched = o; o = align256(o + nslow * 4);
-    L.off_slow_off = o; o = align256(o + nslow * 4);
-    L.off_slow_m = o;  o = align256(o + nslow * 4);
-    L.off_cc = o;      o = align256(o + nslow * 4);
-    L.off_unit_k = o;  o = align256(o + nunits * 4);
-    L.off_unit_c = o;  o = align256(o + nunits * 4);
-    L.off_cl = o;      o = align256(o + n * sizeof(OpEntry));
     L.list_mode = n * 32 <= nb;  // a small batch: apply visits only the touched buckets
     L.total = o;
     return L;
@@ -211,16 +205,11 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     w.inc = reinterpret_cast<uint64_t*>(b + L.off_inc);
     w.sat = reinterpret_cast<uint32_t*>(b + L.off_sat);
     w.sstat = b + L.off_sstat;
+    w.slot_of = reinterpret_cast<uint32_t*>(b + L.off_slot_of);
     w.il = reinterpret_cast<OpEntry*>(b + L.off_il);
     w.ol = reinterpret_cast<OpEntry*>(b + L.off_ol);
     w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);
     w.touched = reinterpret_cast<uint32_t*>(b + L.off_touched);
-    w.slow_off = reinterpret_cast<uint32_t*>(b + L.off_slow_off);
-    w.slow_m = reinterpret_cast<uint32_t*>(b + L.off_slow_m);
-    w.cc = reinterpret_cast<uint32_t*>(b + L.off_cc);
-    w.unit_k = reinterpret_cast<uint32_t*>(b + L.off_unit_k);
-    w.unit_c = reinterpret_cast<uint32_t*>(b + L.off_unit_c);
-    w.cl = reinterpret_cast<OpEntry*>(b + L.off_cl);
     w.P = L.P;
     w.logP = L.logP;
     w.cap = L.cap;

@@ -10,20 +10,16 @@
 //     bmin   u64[B][2]            (score, key) of a full bucket's minimum entry; key 0 = not known
 //     clock  u64                  LRU logical clock (device-resident so captured graphs advance it)
 //
-//   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity,
-//   S = min(n, B) crowded-bucket slots, U = S + n / kSlowUnit + 1 work units):
+//   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity):
 //     zeroed on entry: dd {key u64, last u32, claim u32}[P], okey u64[P], ctr u32[64],
 //                      and for LFU inc u64[P], sat u32[P]
-//     sstat u8[P]                      status of each distinct key of a crowded bucket
-//     il OpEntry[B*C]                  per-bucket operation lists, one entry per occurrence: key,
-//                                      score input (custom score / LFU increment / LRU clock),
+//     sstat u8[P]                      status of each distinct key's operation
+//     slot_of u32[n]                   dedupe slot of input i (or kNoSlot)
+//     il OpEntry[B*C]                  per-bucket operation lists: key, new score,
 //                                      (dedupe slot << 32 | input position), slot (0xFF = insert)
 //     ol OpEntry[P]                    list positions >= C, hashed on (bucket, position) via okey
-//     slow u32[S]                      buckets with more operations than the fast path takes
-//     touched u32[S]                   buckets that received an operation (small batches only)
-//     slow_off, slow_m, cc u32[S]      crowded buckets: region in cl, operations, distinct keys
-//     unit_k, unit_c u32[U]            crowded-bucket work units (bucket index, chunk)
-//     cl OpEntry[n]                    distinct-key operations of the crowded buckets
+//     slow u32[min(n, B)]              buckets with more operations than the fast path takes
+//     touched u32[min(n, B)]           buckets that received an operation (small batches only)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,8 +33,7 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint8_t kInsertSlot = 0xFF;
 constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
-enum Counter { kCtrSlow = 0, kCtrTouched = 1, kCtrItems = 2, kCtrUnits = 3 };
-constexpr uint32_t kSlowUnit = 512;  // operations of a crowded bucket per wave-sized work unit
+enum Counter { kCtrSlow = 0, kCtrTouched = 1 };
 
 struct TableView {
     uint8_t* dig;
@@ -75,16 +70,11 @@ struct UpsertWs {
     uint64_t* inc;
     uint32_t* sat;
     uint8_t* sstat;
+    uint32_t* slot_of;
     OpEntry* il;
     OpEntry* ol;
     uint32_t* slow;
     uint32_t* touched;
-    uint32_t* slow_off;  // per crowded bucket: start of its region in `cl`
-    uint32_t* slow_m;    // per crowded bucket: operations routed to it
-    uint32_t* cc;        // per crowded bucket: distinct keys appended to its region
-    uint32_t* unit_k;    // per work unit: crowded bucket index
-    uint32_t* unit_c;    // per work unit: chunk of kSlowUnit operations
-    OpEntry* cl;         // distinct-key operations of the crowded buckets
     uint64_t P;
     int logP;
     uint32_t cap;    // inline operations per bucket
@@ -122,8 +112,7 @@ struct StorageLayout {
 
 struct UpsertLayout {
     size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_zero_end, off_zero_end_lfu;
-    size_t off_sstat, off_il, off_ol, off_slow, off_touched, off_slow_off, off_slow_m, off_cc;
-    size_t off_unit_k, off_unit_c, off_cl, total;
+    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, off_touched, total;
     uint64_t P;
     int logP;
     uint32_t cap;
@@ -148,15 +137,15 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
 hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                         uint32_t* ws_slot, int group, hipStream_t s);
 // the phases of an upsert / erase, for callers that order them with events (batched programs):
-// prep (scratch clear) touches only the scratch; route only reads the table (and writes the
-// scratch, the eviction count and the statuses of reserved keys); apply writes the table and the
+// prep (scratch clear, dedupe) and route only read the table; apply writes it; finish writes the
 // statuses; an erase probe reads, its clear writes
-hipError_t launch_upsert_prep(size_t zero_bytes, const UpsertWs& w, hipStream_t s);
+hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                              const uint64_t* scores, const EvictOut& ev, size_t zero_bytes, hipStream_t s);
 hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
-                               const uint64_t* scores, uint8_t* status, uint64_t* ev_count, int group,
-                               hipStream_t s);
+                               const uint64_t* scores, int group, hipStream_t s);
 hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals,
-                               uint8_t* status, const EvictOut& ev, hipStream_t s);
+                               const EvictOut& ev, hipStream_t s);
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s);
 hipError_t launch_erase_probe(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                               uint32_t* ws_slot, int group, hipStream_t s);
 hipError_t launch_erase_clear(const TableView& t, uint64_t n, uint32_t* ws_slot, hipStream_t s);

@@ -40,9 +40,9 @@ struct Segment {
 };
 
 // Phases of the overlapped form.  A find run is one phase; an erase is probe (reader) + clear
-// (writer); an upsert is prep (scratch clear: touches only its scratch slot), route (reader of
-// the table) and apply (writer, also of the statuses).
-enum PhaseKind { kPhFind, kPhProbe, kPhClear, kPhPrep, kPhRoute, kPhApply };
+// (writer); an upsert is prep (scratch clear + dedupe: touches only its scratch slot), route
+// (reader of the table), apply (writer) and finish (status gather, scratch only).
+enum PhaseKind { kPhFind, kPhProbe, kPhClear, kPhPrep, kPhRoute, kPhApply, kPhFinish };
 enum Lane { kLaneRead = 0, kLaneWrite = 1, kLanePrep = 2 };  // kLanePrep + scratch slot
 
 struct Phase {
@@ -233,8 +233,10 @@ static void build_phases(cskv_program* p) {
         const int apply = add(kPhApply, kLaneWrite, s, j, w);
         readers.clear();
         last_writer = apply;
-        slot_free[j] = apply;
-        seg_end[s] = apply;
+        int end = apply;
+        if (p->ops[g.first].flags) end = add(kPhFinish, kLanePrep + j, s, j, {apply});
+        slot_free[j] = end;
+        seg_end[s] = end;
     }
     // a phase signals when a phase on another lane waits for it, or when it is its lane's last
     int lane_last[kLanes];
@@ -458,11 +460,10 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
     const int rc = plan_upsert(t, a, scratch, p->scratch_bytes, &w, &zero_bytes);
     if (rc != CSKV_OK) return rc;
     switch (ph.kind) {
-        case kPhPrep: e = launch_upsert_prep(zero_bytes, w, s); break;
-        case kPhRoute:
-            e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, a.status, a.ev.count, t->route_group, s);
-            break;
-        default: e = launch_upsert_apply(t->view, w, a.n, a.vals, a.status, a.ev, s); break;
+        case kPhPrep: e = launch_upsert_prep(t->view, w, a.n, a.keys, a.scores, a.ev, zero_bytes, s); break;
+        case kPhRoute: e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, t->route_group, s); break;
+        case kPhApply: e = launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s); break;
+        default: e = launch_upsert_finish(w, a.n, a.status, s); break;
     }
     return e == hipSuccess ? CSKV_OK : CSKV_EHIP;
 }

@@ -4,22 +4,19 @@
 //
 // One call is a fixed sequence on one stream:
 //   zero     one fill of the call's scratch (dedupe set, overflow keys, counters)
-//   route    G lanes per occurrence, against the table as it was before the call: update slot
+//   dedupe   one set entry per distinct key (one CAS per distinct key; atomicMax only for
+//            repeats): last occurrence, LFU increment sum
+//   route    G lanes per distinct key, against the table as it was before the call: update slot
 //            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
-//            smaller cached bucket minimum (score, key)); the occurrence is appended to the
-//            target bucket's list (rank from an atomic count per bucket).  Routing depends only
-//            on the key and the pre-call table, so every occurrence of a key lands in the same
-//            list: duplicates are resolved per bucket, after routing
-//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block, for buckets
-//            with at most 16 occurrences: duplicates collapse to the last occurrence (LWW; LFU
-//            increments summed), then updates, then inserts ranked by (score desc, key asc):
-//            the first ones take free slots, the rest compete with the smallest residents by
-//            (score, key) - strict admission; victims are copied out, slots written, the bucket
-//            minimum cached when full; every occurrence's status written.  A crowded bucket is
-//            registered with its work units instead
-//   crowded  (three passes over the crowded buckets' occurrences, wave-sized units, then one wave
-//            per bucket) dedupe through a hash set, compaction of one operation per distinct key,
-//            the same rules with the best 128 inserts kept in LDS, and the statuses
+//            smaller cached bucket minimum (score, key)); the operation is appended to the
+//            target bucket's list (rank from an atomic count per bucket)
+//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block: updates,
+//            then inserts ranked by (score desc, key asc): the first ones take free slots, the
+//            rest compete with the smallest residents by (score, key) - strict admission;
+//            victims are copied out, slots written, the bucket minimum cached when full
+//   slow     one wave per bucket that received more than 16 operations: same rules, with the
+//            best 128 inserts kept in LDS
+//   finish   per-occurrence status
 // Every write to a table slot's key/score/digest is made by the lane that owns the slot, and
 // every 16-byte chunk c of a row by lane c mod (lanes), so writes that must follow one another
 // (an update, then the eviction of the same entry) are ordered by program order.
@@ -61,30 +58,63 @@ __device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t s
     q[1] = make_ulonglong2(w, (unsigned long long)slot);
 }
 
-__device__ __forceinline__ OpEntry* entry_ptr(const UpsertWs& w, uint32_t b, uint32_t r) {
-    if (r < w.cap) return w.il + (size_t)b * w.cap + r;
+__device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
+    if (r < w.cap) return load_entry(w.il + (size_t)b * w.cap + r);
     const uint64_t ok = overflow_key(b, r);
     uint64_t q = scratch_hash(ok, w.logP);
     for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
-    return w.ol + q;
+    return load_entry(w.ol + q);
 }
 
-__device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) { return load_entry(entry_ptr(w, b, r)); }
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
+                                                const uint64_t* __restrict__ scores, uint64_t* ev_count) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && ev_count) *ev_count = 0;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    if (reserved_key(k)) {
+        w.slot_of[i] = kNoSlot;
+        return;
+    }
+    // one atomic per distinct key: the occurrence that claims the entry records its index with a
+    // plain store; later occurrences of the key raise `last` with atomicMax
+    const uint64_t mask = w.P - 1;
+    uint64_t p = scratch_hash(k, w.logP);
+    for (uint64_t probes = 0; probes < w.P; ++probes) {
+        const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[p].key), 0ull,
+                                                 (unsigned long long)k);
+        if (old == 0ull) {
+            w.dd[p].claim = (uint32_t)(i + 1);
+            break;
+        }
+        if (old == k) {
+            atomicMax(&w.dd[p].last, (uint32_t)(i + 1));
+            break;
+        }
+        p = (p + 1) & mask;
+    }
+    w.slot_of[i] = (uint32_t)p;
+    if (t.policy == 2) {  // LFU: saturating sum of the increments
+        const uint64_t inc = scores ? scores[i] : 1ull;
+        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + p), (unsigned long long)inc);
+        if (old + inc < old) atomicOr(w.sat + p, 1u);
+    }
+}
 
 // ------------------------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                               const uint64_t* __restrict__ scores, uint8_t* __restrict__ status,
-                                               uint64_t* ev_count) {
+                                               const uint64_t* __restrict__ scores) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     if (i >= n) return;
     const int lane = glane<G>();
-    if (i == 0 && lane == 0 && ev_count) *ev_count = 0;
+    const uint32_t p = w.slot_of[i];
+    if (p == kNoSlot) return;
+    const DedupeEntry de = w.dd[p];
+    if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
     const uint64_t k = keys[i];
-    if (reserved_key(k)) {
-        if (lane == 0 && status) status[i] = 5;  // INVALID_KEY
-        return;
-    }
+    const uint64_t clock = *t.clock + 1;  // LRU: this call's clock (advanced after routing)
     const KeyHash h = hash_key(t, k);
     const bool two = h.b2 != h.b1;
     LineSeg<G> s1, s2;
@@ -96,13 +126,14 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         slot = verify<G>(t, h.b2, s2.match(h.dg), k, lane);
         tgt = h.b2;
     }
-    // the occurrence's score input: its custom score, the LRU clock of this call, or its LFU increment
-    uint64_t sc;
-    if (t.policy == 0) sc = scores[i];
-    else if (t.policy == 1) sc = *t.clock + 1;  // advanced after routing
-    else sc = scores ? scores[i] : 1ull;
+    uint64_t inc = 0;
+    if (t.policy == 2) inc = w.sat[p] ? ~0ull : w.inc[p];
+    uint64_t ns;
     uint8_t islot;
     if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
+        if (t.policy == 0) ns = scores[i];
+        else if (t.policy == 1) ns = clock;
+        else ns = sat_add(t.scores[(size_t)tgt * kSlots + slot], inc);
         islot = (uint8_t)slot;
     } else {  // INSERT: candidate choice (Alg. 3)
         tgt = h.b1;
@@ -119,13 +150,17 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
                 if (m2s < m1s || (m2s == m1s && m2k < m1k)) tgt = h.b2;
             }
         }
+        if (t.policy == 0) ns = scores[i];
+        else if (t.policy == 1) ns = clock;
+        else ns = inc;
         islot = kInsertSlot;
     }
     if (lane == 0) {
         const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
         if (w.list_mode && r == 0) w.touched[atomicAdd(w.ctr + kCtrTouched, 1u)] = tgt;
+        const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         if (r < w.cap) {
-            store_entry(w.il + (size_t)tgt * w.cap + r, k, sc, i, islot);
+            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot);
         } else {
             const uint64_t ok = overflow_key(tgt, r);
             uint64_t q = scratch_hash(ok, w.logP);
@@ -135,7 +170,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
                 if (old == 0ull) break;
                 q = (q + 1) & (w.P - 1);
             }
-            store_entry(w.ol + q, k, sc, i, islot);
+            store_entry(w.ol + q, k, ns, wv, islot);
         }
     }
 }
@@ -156,10 +191,8 @@ __device__ __forceinline__ int nth_bit128(uint64_t lo, uint64_t hi, int r) {
 }
 
 constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
-constexpr int kSpecEntries = 4;   // list entries loaded before the bucket's count is known
 
-__global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev,
-                                                    uint8_t* __restrict__ status) {
+__global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint32_t s_nev[kApplyGroups];
     __shared__ uint32_t s_off[kApplyGroups];
     __shared__ unsigned long long s_base;
@@ -169,40 +202,17 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
     if (w.list_mode) bb = bb < w.ctr[kCtrTouched] ? w.touched[bb] : t.nbuckets;
     const uint32_t b = (uint32_t)bb;
-    // the count, the first inline entries (one 128-byte line) and the digest line do not depend
-    // on one another: all three loads are issued before the first is needed (entries past the
-    // count are never used; later entries are loaded once the count is known)
     uint32_t m = 0;
-    Entry spec{0, 0, 0, kInsertSlot};
-    uint2 dv = make_uint2(0u, 0u);
-    const uint32_t nspec = w.cap < (uint32_t)kSpecEntries ? w.cap : (uint32_t)kSpecEntries;
-    if (bb < t.nbuckets) {
-        m = t.cnt[b];
-        if ((uint32_t)lane < nspec) spec = load_entry(w.il + (size_t)b * w.cap + lane);
-        dv = *reinterpret_cast<const uint2*>(t.dig + (size_t)b * kSlots + lane * SPL);
-    }
-    if (m > (uint32_t)kFastMax) {  // crowded: register the bucket, its cl region and its work units
-        if (lane == 0) {
-            const uint32_t k = atomicAdd(w.ctr + kCtrSlow, 1u);
-            w.slow[k] = b;
-            w.slow_m[k] = m;
-            w.slow_off[k] = atomicAdd(w.ctr + kCtrItems, m);
-            w.cc[k] = 0;
-            const uint32_t units = (m + kSlowUnit - 1) / kSlowUnit;
-            const uint32_t u0 = atomicAdd(w.ctr + kCtrUnits, units);
-            for (uint32_t u = 0; u < units; ++u) {
-                w.unit_k[u0 + u] = k;
-                w.unit_c[u0 + u] = u;
-            }
-        }
+    if (bb < t.nbuckets) m = t.cnt[b];
+    if (m > (uint32_t)kFastMax) {
+        if (lane == 0) w.slow[atomicAdd(w.ctr + kCtrSlow, 1u)] = b;
         m = 0;
     }
     const size_t eb = (size_t)b * kSlots;
 
     // state carried over the block barrier
     Entry e{0, 0, 0, kInsertSlot};
-    bool has = false, is_upd = false, is_ins = false, evicts = false;
-    int rep_lane = lane;
+    bool is_upd = false, is_ins = false, evicts = false;
     int new_slot = -1, evi = 0;
     uint64_t vkey = 0, vscore = 0;
     uint32_t taken = 0, upd_bits = 0, ins_bits = 0;
@@ -211,35 +221,11 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     uint32_t nev = 0;
 
     if (m > 0) {
-        has = lane < (int)m;
-        if (has) e = (uint32_t)lane < nspec ? spec : fetch_entry(w, b, (uint32_t)lane);
-        // every occurrence of a key is in this list: the last one (largest input position) stands
-        // for the key (LWW); LFU increments of all occurrences are summed, saturating
-        const uint32_t pos = (uint32_t)e.w;
-        uint32_t best = pos;
-        uint64_t lsum = e.score;
-        bool lsat = false;
-        for (int y = 0; y < (int)m; ++y) {
-            const uint64_t ky = __shfl(e.key, y, GA);
-            const uint32_t py = (uint32_t)__shfl((int)pos, y, GA);
-            const uint64_t sy = __shfl(e.score, y, GA);
-            if (has && y != lane && ky == e.key) {
-                if (py > best) {
-                    best = py;
-                    rep_lane = y;
-                }
-                const uint64_t s2 = lsum + sy;
-                lsat |= s2 < lsum;
-                lsum = s2;
-            }
-        }
-        const bool rep = has && rep_lane == lane;
-        if (rep && t.policy == 2) {  // LFU: the summed increment, added to the resident score on update
-            const uint64_t inc = lsat ? ~0ull : lsum;
-            e.score = e.slot != kInsertSlot ? sat_add(t.scores[eb + e.slot], inc) : inc;
-        }
-        is_upd = rep && e.slot != kInsertSlot;
-        is_ins = rep && e.slot == kInsertSlot;
+        const bool has = lane < (int)m;
+        if (has) e = fetch_entry(w, b, (uint32_t)lane);
+        is_upd = has && e.slot != kInsertSlot;
+        is_ins = has && e.slot == kInsertSlot;
+        const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
         const uint32_t emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
         const int occ = kSlots - gsum_i<GA>(__popc(emask8));
         const int nfree = kSlots - occ;
@@ -340,12 +326,9 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     if (m == 0) return;
     const uint64_t ev_base = ev.count ? s_base + s_off[g] : 0ull;
 
-    // statuses of every occurrence (that of its key's last occurrence), evicted (key, score)
-    {
-        const int st = is_upd ? 1 : (is_ins ? (new_slot < 0 ? 4 : (evicts ? 3 : 2)) : 0);
-        const int stx = __shfl(st, rep_lane, GA);
-        if (has && status) status[(uint32_t)e.w] = (uint8_t)stx;
-    }
+    // statuses and evicted (key, score)
+    if (is_upd) w.sstat[e.w >> 32] = 1;  // UPDATED
+    if (is_ins) w.sstat[e.w >> 32] = new_slot < 0 ? 4 : (evicts ? 3 : 2);
     if (evicts && ev.keys) {
         ev.keys[ev_base + evi] = vkey;
         ev.scores[ev_base + evi] = vscore;
@@ -374,63 +357,34 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             }
         }
     }
-    // rows: chunk c of every row by lane c mod 16; updates before evictions.  Two rows at a time,
-    // both loads before both stores (the two slots differ: updates hit distinct slots, inserts
-    // distinct new slots, each of which is its own victim's slot)
+    // rows: chunk c of every row by lane c mod 16; updates before evictions
     const uint32_t chunks = t.dim >> 2;
-    for (uint32_t ub = upd_bits; ub;) {
-        const int x0 = __ffs(ub) - 1;
-        ub &= ub - 1;
-        const bool two = ub != 0;
-        const int x1 = two ? __ffs(ub) - 1 : x0;
-        if (two) ub &= ub - 1;
-        const int us0 = __shfl((int)e.slot, x0, GA), us1 = __shfl((int)e.slot, x1, GA);
-        const uint32_t p0 = (uint32_t)__shfl((int)(uint32_t)e.w, x0, GA);
-        const uint32_t p1 = (uint32_t)__shfl((int)(uint32_t)e.w, x1, GA);
-        uint4* d0 = reinterpret_cast<uint4*>(t.vals + (eb + us0) * t.dim);
-        uint4* d1 = reinterpret_cast<uint4*>(t.vals + (eb + us1) * t.dim);
-        const uint4* s0 = reinterpret_cast<const uint4*>(vals + (size_t)p0 * t.dim);
-        const uint4* s1 = reinterpret_cast<const uint4*>(vals + (size_t)p1 * t.dim);
-        for (uint32_t c = lane; c < chunks; c += GA) {
-            const uint4 a0 = s0[c];
-            const uint4 a1 = two ? s1[c] : a0;
-            d0[c] = a0;
-            if (two) d1[c] = a1;
-        }
+    for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
+        const int x = __ffs(ub) - 1;
+        const int us = __shfl((int)e.slot, x, GA);
+        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
+        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+        for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
     }
-    uint32_t placed = 0;  // inserts that took a slot
     for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
         const int x = __ffs(ib) - 1;
-        if (__shfl(new_slot, x, GA) >= 0) placed |= 1u << x;
-    }
-    for (uint32_t ib = placed; ib;) {
-        const int x0 = __ffs(ib) - 1;
-        ib &= ib - 1;
-        const bool two = ib != 0;
-        const int x1 = two ? __ffs(ib) - 1 : x0;
-        if (two) ib &= ib - 1;
-        const int n0 = __shfl(new_slot, x0, GA), n1 = __shfl(new_slot, x1, GA);
-        const uint32_t p0 = (uint32_t)__shfl((int)(uint32_t)e.w, x0, GA);
-        const uint32_t p1 = (uint32_t)__shfl((int)(uint32_t)e.w, x1, GA);
-        const bool v0 = ev.vals && __shfl((int)evicts, x0, GA) != 0;
-        const bool v1 = two && ev.vals && __shfl((int)evicts, x1, GA) != 0;
-        const int i0 = __shfl(evi, x0, GA), i1 = __shfl(evi, x1, GA);
-        uint4* d0 = reinterpret_cast<uint4*>(t.vals + (eb + n0) * t.dim);
-        uint4* d1 = reinterpret_cast<uint4*>(t.vals + (eb + n1) * t.dim);
-        const uint4* s0 = reinterpret_cast<const uint4*>(vals + (size_t)p0 * t.dim);
-        const uint4* s1 = reinterpret_cast<const uint4*>(vals + (size_t)p1 * t.dim);
-        uint4* o0 = reinterpret_cast<uint4*>(ev.vals + (ev_base + i0) * t.dim);
-        uint4* o1 = reinterpret_cast<uint4*>(ev.vals + (ev_base + i1) * t.dim);
-        for (uint32_t c = lane; c < chunks; c += GA) {
-            const uint4 a0 = s0[c];
-            const uint4 a1 = two ? s1[c] : a0;
-            uint4 q0 = a0, q1 = a0;
-            if (v0) q0 = d0[c];  // evicted rows are copied out before they are overwritten
-            if (v1) q1 = d1[c];
-            if (v0) o0[c] = q0;
-            if (v1) o1[c] = q1;
-            d0[c] = a0;
-            if (two) d1[c] = a1;
+        const int ns = __shfl(new_slot, x, GA);
+        if (ns < 0) continue;
+        const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+        const bool xe = __shfl((int)evicts, x, GA) != 0;
+        const int xi = __shfl(evi, x, GA);
+        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + ns) * t.dim);
+        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+        if (xe && ev.vals) {
+            uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) {
+                const uint4 old = dst[c];
+                out[c] = old;
+                dst[c] = src[c];
+            }
+        } else {
+            for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
         }
     }
     // cached minimum of a full bucket (exact; every slot is occupied now).  Keys are read back
@@ -458,83 +412,7 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
 }
 
 // ------------------------------------------------------------------------------------------
-// crowded buckets (more than 16 occurrences): dedupe through the hash set, one operation per
-// distinct key, then one wave per bucket
-
-// every occurrence routed to a crowded bucket, one wave per unit of kSlowUnit occurrences
-template <typename F>
-__device__ __forceinline__ void for_each_crowded_op(const UpsertWs& w, F&& f) {
-    const uint32_t nunits = w.ctr[kCtrUnits];
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const uint32_t nwaves = gridDim.x * blockDim.x / 64;
-    const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t u = wave; u < nunits; u += nwaves) {
-        const uint32_t k = w.unit_k[u], c = w.unit_c[u];
-        const uint32_t b = w.slow[k], m = w.slow_m[k];
-        const uint32_t end = m < (c + 1) * kSlowUnit ? m : (c + 1) * kSlowUnit;
-        for (uint32_t r = c * kSlowUnit + lane; r < end; r += 64) f(k, b, r);
-    }
-}
-
-// one set entry per distinct key: the occurrence that claims it records its position with a plain
-// store, later ones raise `last` with atomicMax; LFU increments summed (saturation flagged).  The
-// set slot is recorded in the occurrence's list entry.
-__global__ void __launch_bounds__(256) k_slow_dedupe(TableView t, UpsertWs w) {
-    for_each_crowded_op(w, [&](uint32_t, uint32_t b, uint32_t r) {
-        OpEntry* ep = entry_ptr(w, b, r);
-        const Entry e = load_entry(ep);
-        const uint32_t pos = (uint32_t)e.w;
-        const uint64_t mask = w.P - 1;
-        uint64_t p = scratch_hash(e.key, w.logP);
-        for (uint64_t probes = 0; probes < w.P; ++probes) {
-            const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[p].key), 0ull,
-                                                     (unsigned long long)e.key);
-            if (old == 0ull) {
-                w.dd[p].claim = pos + 1;
-                break;
-            }
-            if (old == e.key) {
-                atomicMax(&w.dd[p].last, pos + 1);
-                break;
-            }
-            p = (p + 1) & mask;
-        }
-        if (t.policy == 2) {
-            const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + p),
-                                                     (unsigned long long)e.score);
-            if (old + e.score < old) atomicOr(w.sat + p, 1u);
-        }
-        ep->w = (p << 32) | pos;
-    });
-}
-
-// the last occurrence of each distinct key is appended to its bucket's cl region, with the final
-// score (LFU: summed increment, added to the resident score on update)
-__global__ void __launch_bounds__(256) k_slow_compact(TableView t, UpsertWs w) {
-    for_each_crowded_op(w, [&](uint32_t k, uint32_t b, uint32_t r) {
-        const Entry e = fetch_entry(w, b, r);
-        const uint32_t p = (uint32_t)(e.w >> 32), pos = (uint32_t)e.w;
-        const DedupeEntry de = w.dd[p];
-        if ((de.claim > de.last ? de.claim : de.last) != pos + 1) return;
-        uint64_t sc = e.score;
-        if (t.policy == 2) {
-            const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
-            sc = e.slot != kInsertSlot ? sat_add(t.scores[(size_t)b * kSlots + e.slot], inc) : inc;
-        }
-        const uint32_t at = atomicAdd(w.cc + k, 1u);
-        store_entry(w.cl + w.slow_off[k] + at, e.key, sc, e.w, e.slot);
-    });
-}
-
-// every occurrence routed to a crowded bucket takes its key's status
-__global__ void __launch_bounds__(256) k_slow_status(UpsertWs w, uint8_t* __restrict__ status) {
-    for_each_crowded_op(w, [&](uint32_t, uint32_t b, uint32_t r) {
-        const Entry e = fetch_entry(w, b, r);
-        status[(uint32_t)e.w] = w.sstat[e.w >> 32];
-    });
-}
-
-// slow apply: one wave per crowded bucket, over its distinct keys
+// slow apply: one wave per bucket with more than 16 operations
 __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint64_t cs[192], ck[192], cw[192];  // insert candidates: score, key, w
     __shared__ uint64_t ns_[128], nk_[128], nw_[128];
@@ -551,8 +429,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (uint32_t si = blockIdx.x; si < nslow; si += gridDim.x) {
         const uint32_t b = w.slow[si];
-        const uint32_t m = w.cc[si];  // distinct keys (one operation each)
-        const OpEntry* list = w.cl + w.slow_off[si];
+        const uint32_t m = t.cnt[b];
         const size_t eb = (size_t)b * kSlots;
 
         // residents
@@ -576,7 +453,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const bool has = c0 + lane < m;
             Entry e{0, 0, 0, kInsertSlot};
-            if (has) e = load_entry(list + c0 + lane);
+            if (has) e = fetch_entry(w, b, c0 + lane);
             const bool upd = has && e.slot != kInsertSlot;
             const bool ins = has && e.slot == kInsertSlot;
             if (upd) {
@@ -765,53 +642,64 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
 }
 
 // ------------------------------------------------------------------------------------------
-template <int G>
-static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
-                         uint8_t* status, uint64_t* ev_count, hipStream_t s) {
-    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, status, ev_count);
+__global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t* __restrict__ status) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = w.slot_of[i];
+    status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
 }
 
-hipError_t launch_upsert_prep(size_t zero_bytes, const UpsertWs& w, hipStream_t s) {
-    return launch_fill_zero(w.dd, zero_bytes, s);
+template <int G>
+static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
+                         hipStream_t s) {
+    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores);
+}
+
+hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                              const uint64_t* scores, const EvictOut& ev, size_t zero_bytes, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipError_t e = launch_fill_zero(w.dd, zero_bytes, s);
+    if (e != hipSuccess) return e;
+    k_dedupe<<<blocks_for(n, 256), 256, 0, s>>>(t, w, n, keys, scores, ev.count);
+    return hipGetLastError();
 }
 
 hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
-                               const uint64_t* scores, uint8_t* status, uint64_t* ev_count, int group, hipStream_t s) {
+                               const uint64_t* scores, int group, hipStream_t s) {
     if (n == 0) return hipSuccess;
     switch (group) {
-        case 4: launch_route<4>(t, w, n, keys, scores, status, ev_count, s); break;
-        case 16: launch_route<16>(t, w, n, keys, scores, status, ev_count, s); break;
-        default: launch_route<8>(t, w, n, keys, scores, status, ev_count, s); break;
+        case 4: launch_route<4>(t, w, n, keys, scores, s); break;
+        case 16: launch_route<16>(t, w, n, keys, scores, s); break;
+        default: launch_route<8>(t, w, n, keys, scores, s); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals, uint8_t* status,
-                               const EvictOut& ev, hipStream_t s) {
+hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals, const EvictOut& ev,
+                               hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint64_t visit = w.list_mode ? (n < t.nbuckets ? n : t.nbuckets) : t.nbuckets;
-    k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev, status);
-    // crowded buckets: grids sized for the most work units a call can have, striding over the
-    // units the fast kernel registered
-    const uint64_t nslow = n < t.nbuckets ? n : t.nbuckets;
-    const uint64_t units = nslow + n / kSlowUnit + 1;
-    const unsigned ublocks = (unsigned)((units + 3) / 4 < 256 ? (units + 3) / 4 : 256);
-    k_slow_dedupe<<<ublocks, 256, 0, s>>>(t, w);
-    k_slow_compact<<<ublocks, 256, 0, s>>>(t, w);
-    const unsigned slow_blocks = (unsigned)(nslow < 1024 ? nslow : 1024);
-    k_apply_slow<<<slow_blocks, 64, 0, s>>>(t, w, vals, ev);
-    if (status) k_slow_status<<<ublocks, 256, 0, s>>>(w, status);
+    k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
+    uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
+    if (slow_blocks > 2048) slow_blocks = 2048;
+    k_apply_slow<<<(unsigned)slow_blocks, 64, 0, s>>>(t, w, vals, ev);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s) {
+    if (n == 0 || !status) return hipSuccess;
+    k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status);
     return hipGetLastError();
 }
 
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
                          const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
                          hipStream_t s) {
-    if (n == 0) return hipSuccess;
     hipError_t e;
-    if ((e = launch_upsert_prep(zero_bytes, w, s)) != hipSuccess) return e;
-    if ((e = launch_upsert_route(t, w, n, keys, scores, status, ev.count, group, s)) != hipSuccess) return e;
-    return launch_upsert_apply(t, w, n, vals, status, ev, s);
+    if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
+    if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
+    if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
+    return launch_upsert_finish(w, n, status, s);
 }
 
 }  // namespace cskv
