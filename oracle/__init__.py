@@ -55,6 +55,14 @@ def _load():
     lib.ora_erase.argtypes = [P, U64, P, P]
     lib.ora_export.restype = U64
     lib.ora_export.argtypes = [P, U64, U64, P, P, P, P]
+    lib.ora_contains.argtypes = [P, U64, P, P]
+    lib.ora_locate.argtypes = [P, U64, P, P, P]
+    lib.ora_assign.restype = ctypes.c_long
+    lib.ora_assign.argtypes = [P, U64, P, P, P, P]
+    lib.ora_find_or_insert.restype = ctypes.c_long
+    lib.ora_find_or_insert.argtypes = [P, U64, P, P, P, P, P]
+    lib.ora_export_if.restype = U64
+    lib.ora_export_if.argtypes = [P, U64, U64, U64, P, P, P, P]
     lib.ora_stats.argtypes = [P, P]
     lib.ora_reset_stats.argtypes = [P]
     _lib = lib
@@ -140,6 +148,52 @@ class Oracle:
         s = np.zeros(cap, dtype=np.uint64)
         b = np.zeros(cap, dtype=np.uint64)
         c = int(self.lib.ora_export(self.h, b0, b1, _p(k), _p(v), _p(s), _p(b)))
+        return k[:c], v[:c], s[:c], b[:c]
+
+    def contains(self, keys):
+        keys = _u64(keys)
+        found = np.zeros(keys.size, dtype=np.uint8)
+        self.lib.ora_contains(self.h, keys.size, _p(keys), _p(found))
+        return found
+
+    def locate(self, keys):
+        """(found u8[n], bucket u64[n]) - the bucket of each resident key (0 where absent)."""
+        keys = _u64(keys)
+        found = np.zeros(keys.size, dtype=np.uint8)
+        buckets = np.zeros(keys.size, dtype=np.uint64)
+        self.lib.ora_locate(self.h, keys.size, _p(keys), _p(found), _p(buckets))
+        return found, buckets
+
+    def assign(self, keys, vids=None, scores=None):
+        """assign (vids given) or assign_scores (vids None); returns found u8[n]."""
+        keys = _u64(keys)
+        v = None if vids is None else _u64(vids)
+        sc = None if scores is None else _u64(scores)
+        found = np.zeros(keys.size, dtype=np.uint8)
+        if self.lib.ora_assign(self.h, keys.size, _p(keys), _p(v), _p(sc), _p(found)) < 0:
+            raise ValueError("oracle assign rejected its arguments")
+        return found
+
+    def find_or_insert(self, keys, vids, scores=None):
+        """Returns (status u8[n], out_vids u64[n])."""
+        keys = _u64(keys)
+        vids = _u64(vids)
+        sc = None if scores is None else _u64(scores)
+        status = np.zeros(keys.size, dtype=np.uint8)
+        out = np.zeros(keys.size, dtype=np.uint64)
+        if self.lib.ora_find_or_insert(self.h, keys.size, _p(keys), _p(vids), _p(sc), _p(status), _p(out)) < 0:
+            raise ValueError("oracle find_or_insert rejected its arguments")
+        return status, out
+
+    def export_if(self, min_score: int, b0: int = 0, b1: int | None = None):
+        """(keys, vids, scores, buckets) of the entries in buckets [b0, b1) with score >= min_score."""
+        b1 = self.B if b1 is None else b1
+        cap = max(1, (b1 - b0) * self.S)
+        k = np.zeros(cap, dtype=np.uint64)
+        v = np.zeros(cap, dtype=np.uint64)
+        s = np.zeros(cap, dtype=np.uint64)
+        b = np.zeros(cap, dtype=np.uint64)
+        c = int(self.lib.ora_export_if(self.h, b0, b1, int(min_score), _p(k), _p(v), _p(s), _p(b)))
         return k[:c], v[:c], s[:c], b[:c]
 
     def stats(self):

@@ -44,6 +44,21 @@
  *   erase: every present key is removed; erased[i] tells whether key[i] was present
  *   before the call.  size: number of entries.  export: all entries of a bucket range.
  *
+ *   The rest of the API named by Sec. 3.5's role list and Sec. 4.1:
+ *   contains (reader): found[i] tells whether key[i] is resident.
+ *   locate (reader): found[i] and the bucket of a resident key (the oracle models no slots;
+ *     the GPU's position-returning find is checked against this bucket).
+ *   assign / assign_scores (updaters: values or scores of existing entries, never bucket
+ *     structure): LRU clock +1 per call; duplicates collapse to the last occurrence (value
+ *     and CUSTOM score), LFU increments summed; a resident key's score is set as an UPDATE of
+ *     insert_or_assign sets it and (assign only) its value-id replaced; absent keys change
+ *     nothing; found[i] tells whether key[i] is resident.
+ *   find_or_insert (inserter): insert_or_assign in which a resident key keeps its value-id
+ *     (only its score is updated); out_vids[i] is key[i]'s value-id if it was resident before
+ *     the call, else its last occurrence's value-id (inserted or rejected alike; a resident
+ *     key that the same call then evicts still returns the value it had).
+ *   export_if: the entries of a bucket range whose score is at least a threshold.
+ *
  * Readings where the paper is silent or inconsistent (the batch order above, strict
  * admission, (score, key) victim order, digest bits, second hash, reserved words) are the
  * ones listed with the design notes of this repository.
@@ -203,6 +218,7 @@ typedef struct {
     int kind;   /* 1 = UPDATE, 2 = INSERT */
     uint64_t inc;
     int status;
+    uint64_t out_vid; /* find_or_insert: the resident value-id, else the batch's */
 } ora_op;
 
 static uint64_t dd_find(dd_slot* m, uint64_t mask, uint64_t key) {
@@ -225,9 +241,9 @@ static int cmp_insert(const void* pa, const void* pb) {
  * it; LFU then uses increment 1; CUSTOM requires it).  status, ev_* may be NULL.
  * Returns the number of evicted entries, or -1 on bad arguments / allocation failure.
  */
-long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,
-                const uint64_t* scores, uint8_t* status, uint64_t* ev_keys, uint64_t* ev_vids,
-                uint64_t* ev_scores) {
+static long upsert_core(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,
+                        const uint64_t* scores, uint8_t* status, uint64_t* ev_keys, uint64_t* ev_vids,
+                        uint64_t* ev_scores, int keep_found, uint64_t* out_vids) {
     if (n == 0) return 0;
     if (t->policy == ORA_CUSTOM && !scores) return -1;
     /* 1. clock */
@@ -297,7 +313,8 @@ long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* 
         ora_entry* e = t->e + o->bucket * t->S + o->slot;
         if (t->policy == ORA_LFU) e->score = sat_add(e->score, o->inc);
         else e->score = o->s_new;
-        e->vid = o->vid;
+        if (!keep_found) e->vid = o->vid;
+        o->out_vid = e->vid;
         o->status = ST_UPDATED;
         t->st_upd++;
     }
@@ -311,6 +328,7 @@ long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* 
     for (long q = 0; q < nins; ++q) {
         ora_op* o = ins[q];
         uint64_t b = o->bucket;
+        o->out_vid = o->vid; /* inserted, or rejected: the key's own value-id */
         ora_entry* be = t->e + b * t->S;
         if (t->cnt[b] < t->S) {
             ora_entry* e = be + t->cnt[b]++;
@@ -343,12 +361,85 @@ long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* 
             status[i] = (uint8_t)ops[m[dd_find(m, cap - 1, keys[i])].op].status;
         }
     }
+    if (out_vids) {
+        for (uint64_t i = 0; i < n; ++i)
+            if (!is_reserved(keys[i])) out_vids[i] = ops[m[dd_find(m, cap - 1, keys[i])].op].out_vid;
+    }
     for (uint64_t i = 0; i < n; ++i)
         if (is_reserved(keys[i])) t->st_invalid++;
     free(ins);
     free(ops);
     free(m);
     return nev;
+}
+
+long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,
+                const uint64_t* scores, uint8_t* status, uint64_t* ev_keys, uint64_t* ev_vids,
+                uint64_t* ev_scores) {
+    return upsert_core(t, n, keys, vids, scores, status, ev_keys, ev_vids, ev_scores, 0, NULL);
+}
+
+/* find_or_insert; out_vids[i] untouched for reserved keys.  Returns 0, or -1 on bad arguments. */
+long ora_find_or_insert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,
+                        const uint64_t* scores, uint8_t* status, uint64_t* out_vids) {
+    long r = upsert_core(t, n, keys, vids, scores, status, NULL, NULL, NULL, 1, out_vids);
+    return r < 0 ? -1 : 0;
+}
+
+/* bucket holding key k, or -1 */
+static long bucket_of(const ora_table* t, uint64_t k) {
+    uint64_t b1 = ora_b1(t, k), b2 = ora_b2(t, k);
+    if (find_in(t, b1, k) >= 0) return (long)b1;
+    if (b2 != b1 && find_in(t, b2, k) >= 0) return (long)b2;
+    return -1;
+}
+
+void ora_contains(const ora_table* t, uint64_t n, const uint64_t* keys, uint8_t* found) {
+    for (uint64_t i = 0; i < n; ++i) found[i] = !is_reserved(keys[i]) && bucket_of(t, keys[i]) >= 0;
+}
+
+void ora_locate(const ora_table* t, uint64_t n, const uint64_t* keys, uint8_t* found, uint64_t* buckets) {
+    for (uint64_t i = 0; i < n; ++i) {
+        long b = is_reserved(keys[i]) ? -1 : bucket_of(t, keys[i]);
+        found[i] = b >= 0;
+        if (b >= 0) buckets[i] = (uint64_t)b;
+    }
+}
+
+/*
+ * assign (vids != NULL) or assign_scores (vids == NULL).  scores as for ora_upsert.
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+long ora_assign(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,
+                const uint64_t* scores, uint8_t* found) {
+    if (n == 0) return 0;
+    if (t->policy == ORA_CUSTOM && !scores) return -1;
+    if (t->policy == ORA_LRU) t->clock += 1;
+    uint64_t cap = 1;
+    while (cap < 2 * n) cap <<= 1;
+    dd_slot* m = (dd_slot*)calloc(cap, sizeof(dd_slot));
+    if (!m) return -1;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t k = keys[i];
+        if (is_reserved(k)) continue;
+        uint64_t p = dd_find(m, cap - 1, k);
+        m[p].key = k;
+        m[p].last = i;
+        if (t->policy == ORA_LFU) m[p].inc = sat_add(m[p].inc, scores ? scores[i] : 1);
+    }
+    for (uint64_t p = 0; p < cap; ++p) {
+        if (m[p].key == 0) continue;
+        long b = bucket_of(t, m[p].key);
+        if (b < 0) continue;
+        ora_entry* e = t->e + (uint64_t)b * t->S + find_in(t, (uint64_t)b, m[p].key);
+        if (t->policy == ORA_CUSTOM) e->score = scores[m[p].last];
+        else if (t->policy == ORA_LRU) e->score = t->clock;
+        else e->score = sat_add(e->score, m[p].inc);
+        if (vids) e->vid = vids[m[p].last];
+    }
+    for (uint64_t i = 0; i < n; ++i) found[i] = !is_reserved(keys[i]) && bucket_of(t, keys[i]) >= 0;
+    free(m);
+    return 0;
 }
 
 void ora_erase(ora_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased) {
@@ -388,6 +479,25 @@ uint64_t ora_export(const ora_table* t, uint64_t b0, uint64_t b1, uint64_t* keys
             if (vids) vids[c] = be[j].vid;
             if (scores) scores[c] = be[j].score;
             if (buckets) buckets[c] = b;
+        }
+    }
+    return c;
+}
+
+/* entries of buckets [b0, b1) with score >= min_score; returns the count */
+uint64_t ora_export_if(const ora_table* t, uint64_t b0, uint64_t b1, uint64_t min_score, uint64_t* keys,
+                       uint64_t* vids, uint64_t* scores, uint64_t* buckets) {
+    uint64_t c = 0;
+    if (b1 > t->B) b1 = t->B;
+    for (uint64_t b = b0; b < b1; ++b) {
+        const ora_entry* be = t->e + b * t->S;
+        for (uint32_t j = 0; j < t->cnt[b]; ++j) {
+            if (be[j].score < min_score) continue;
+            if (keys) keys[c] = be[j].key;
+            if (vids) vids[c] = be[j].vid;
+            if (scores) scores[c] = be[j].score;
+            if (buckets) buckets[c] = b;
+            ++c;
         }
     }
     return c;

@@ -79,9 +79,20 @@ class PyTable:
     # --- Alg. 3 driving Alg. 2, one batch ---
     def upsert(self, keys, vids, scores=None):
         """Returns (status list, evicted list of (key, score, vid))."""
+        st, ev, _ = self._upsert(keys, vids, scores, keep_found=False)
+        return st, ev
+
+    def find_or_insert(self, keys, vids, scores=None):
+        """insert_or_assign in which a resident key keeps its value (its score is updated).
+        Returns (status list, value-id per occurrence: the key's value if it was resident before
+        the call, else its last occurrence's value-id; None for reserved keys)."""
+        st, _, out = self._upsert(keys, vids, scores, keep_found=True)
+        return st, [None if k in (EMPTY, LOCKED) else out[k] for k in keys]
+
+    def _upsert(self, keys, vids, scores, keep_found):
         n = len(keys)
         if n == 0:
-            return [], []
+            return [], [], {}
         if self.policy == LRU:
             self.clock += 1
         # one operation per distinct key
@@ -123,19 +134,22 @@ class PyTable:
                         snap_min[b] = self._min_entry(self.buckets[b])
                 tgt = b2 if snap_min[b2] < snap_min[b1] else b1
             inserts.setdefault(tgt, []).append(k)
-        status = {}
+        status, out = {}, {}
         for b, k in updates:
             ent = self.buckets[b][k]
             if self.policy == LFU:
                 ent[0] = min(M64, ent[0] + inc[k])
             else:
                 ent[0] = s_new[k]
-            ent[1] = vids[last[k]]
+            if not keep_found:
+                ent[1] = vids[last[k]]
+            out[k] = ent[1]
             status[k] = UPDATED
         evicted = []
         for b in sorted(inserts):
             bucket = self.buckets[b]
             for k in sorted(inserts[b], key=lambda x: (-s_new[x], x)):
+                out[k] = vids[last[k]]
                 if len(bucket) < self.S:
                     bucket[k] = [s_new[k], vids[last[k]]]
                     status[k] = INSERTED
@@ -149,7 +163,48 @@ class PyTable:
                 else:
                     status[k] = REJECTED
         st = [INVALID_KEY if k in (EMPTY, LOCKED) else status[k] for k in keys]
-        return st, evicted
+        return st, evicted, out
+
+    # --- readers and updaters of Sec. 3.5's role list ---
+    def contains(self, keys):
+        return [k not in (EMPTY, LOCKED) and self._where(k) is not None for k in keys]
+
+    def locate(self, keys):
+        """bucket of each resident key, None where absent"""
+        return [None if k in (EMPTY, LOCKED) else self._where(k) for k in keys]
+
+    def assign(self, keys, vids=None, scores=None):
+        """assign (vids given) / assign_scores (vids None): resident keys only, last occurrence
+        wins, LFU increments summed; returns per-occurrence residency."""
+        if not keys:
+            return []
+        if self.policy == LRU:
+            self.clock += 1
+        last, inc = {}, {}
+        for i, k in enumerate(keys):
+            if k in (EMPTY, LOCKED):
+                continue
+            last[k] = i
+            if self.policy == LFU:
+                inc[k] = min(M64, inc.get(k, 0) + (scores[i] if scores is not None else 1))
+        for k, i in last.items():
+            b = self._where(k)
+            if b is None:
+                continue
+            ent = self.buckets[b][k]
+            if self.policy == CUSTOM:
+                ent[0] = scores[i]
+            elif self.policy == LRU:
+                ent[0] = self.clock
+            else:
+                ent[0] = min(M64, ent[0] + inc[k])
+            if vids is not None:
+                ent[1] = vids[i]
+        return self.contains(keys)
+
+    def export_if(self, min_score: int):
+        return {b: sorted((k, sv[0], sv[1]) for k, sv in bk.items() if sv[0] >= min_score)
+                for b, bk in enumerate(self.buckets) if any(sv[0] >= min_score for sv in bk.values())}
 
     def erase(self, keys):
         present = [k not in (EMPTY, LOCKED) and self._where(k) is not None for k in keys]

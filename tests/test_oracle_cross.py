@@ -42,10 +42,40 @@ def _run(seed, B, S, mode, policy, n_batches=25):
             st_p, evp = p.upsert(keys, vids, scores)
             assert st_c.tolist() == st_p, (seed, step)
             assert sorted(zip(ek.tolist(), es.tolist(), ev.tolist())) == sorted(evp)
+        elif op < 0.68:
+            vids = list(range(vid, vid + n))
+            vid += n
+            if policy == oracle.CUSTOM:
+                scores = [rng.randint(0, 40) for _ in range(n)]
+            elif policy == oracle.LFU:
+                scores = [rng.choice([1, 2, M64]) for _ in range(n)] if rng.random() < 0.7 else None
+            else:
+                scores = None
+            if rng.random() < 0.5:
+                st_c, out_c = c.find_or_insert(keys, vids, scores)
+                st_p, out_p = p.find_or_insert(keys, vids, scores)
+                assert st_c.tolist() == st_p, (seed, step)
+                assert [int(x) for x, k in zip(out_c, keys) if k not in (0, M64)] == [x for x in out_p if x is not None]
+            else:
+                with_values = rng.random() < 0.5
+                f_c = c.assign(keys, vids if with_values else None, scores)
+                f_p = p.assign(keys, vids if with_values else None, scores)
+                assert f_c.tolist() == [int(x) for x in f_p]
         elif op < 0.8:
             er_c = c.erase(keys)
             er_p = p.erase(keys)
             assert er_c.tolist() == [int(x) for x in er_p]
+        elif op < 0.85:
+            assert c.contains(keys).tolist() == [int(x) for x in p.contains(keys)]
+            fb, bk = c.locate(keys)
+            for i, r in enumerate(p.locate(keys)):
+                assert fb[i] == (r is not None) and (r is None or int(bk[i]) == r)
+            thr = rng.randint(0, 40)
+            kk, vv, ss, bb = c.export_if(thr)
+            got = {}
+            for a_, b_, c_, d_ in zip(kk.tolist(), ss.tolist(), vv.tolist(), bb.tolist()):
+                got.setdefault(int(d_), []).append((int(a_), int(b_), int(c_)))
+            assert {b: sorted(x) for b, x in got.items()} == p.export_if(thr)
         else:
             f, v, s = c.find(keys)
             fp = p.find(keys)
