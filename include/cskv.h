@@ -82,7 +82,8 @@ enum {
 };
 
 /* operation ids for cskv_workspace_bytes */
-enum { CSKV_OP_FIND = 0, CSKV_OP_INSERT_OR_ASSIGN = 1, CSKV_OP_INSERT_AND_EVICT = 2, CSKV_OP_ERASE = 3 };
+enum { CSKV_OP_FIND = 0, CSKV_OP_INSERT_OR_ASSIGN = 1, CSKV_OP_INSERT_AND_EVICT = 2, CSKV_OP_ERASE = 3,
+       CSKV_OP_ASSIGN = 4, CSKV_OP_FIND_OR_INSERT = 5 };
 
 /*
  * Bytes of device storage a table needs (Sec. 3.2 bucket layout, Sec. 3.6 value store):
@@ -167,6 +168,60 @@ int cskv_size(cskv_table* table, uint64_t* d_size, void* stream);
  */
 int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t* d_keys,
                 float* d_values, uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count, void* stream);
+
+/*
+ * export_if (Sec. 4.1's export_batch_if, streaming entries that match a predicate for
+ * checkpointing): as cskv_export, restricted to entries whose score is at least min_score
+ * (min_score 0 = every entry).  Same buffers, capacity and errors as cskv_export.
+ */
+int cskv_export_if(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t min_score,
+                   uint64_t* d_keys, float* d_values, uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count,
+                   void* stream);
+
+/*
+ * contains (reader-group call of Sec. 3.5): d_found[i] (u8) = 1 when d_keys[i] is resident,
+ * else 0 (reserved keys: 0).  No state change; no workspace.  CSKV_EINVAL for n >= 2^31, NULL
+ * or misaligned (8-byte keys) buffers.
+ */
+int cskv_contains(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_found, void* stream);
+
+/*
+ * find_ptr (the position-returning find* of Sec. 5, a reader): d_ptrs[i] (u64) = the device
+ * address of key i's value row inside the table storage (dim floats), 0 when absent; d_found[i]
+ * as contains; d_scores_out[i] (nullable) = its score.  The addresses stay valid until the next
+ * call that changes table structure (an insert, an eviction, erase, clear).  Errors as contains.
+ */
+int cskv_find_ptr(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint64_t* d_ptrs, uint8_t* d_found,
+                  uint64_t* d_scores_out, void* stream);
+
+/*
+ * assign / assign_scores (updater-group calls of Sec. 3.5: values or scores of existing
+ * entries, never bucket structure).  One batch: duplicates collapse to the last occurrence (its
+ * row and CUSTOM score), LFU increments (d_scores, or 1 each when NULL) are summed; a resident
+ * key's score is set as an UPDATE of insert_or_assign sets it (CUSTOM: the score; LRU: this
+ * call's clock, which advances by one per non-empty call; LFU: old + sum, saturating) and
+ * assign also replaces its row with d_values (n x dim fp32); absent keys change nothing.
+ * d_found (nullable) = residency per occurrence.  d_ws: cskv_workspace_bytes(table,
+ * CSKV_OP_ASSIGN, n) bytes.  CSKV_EINVAL as insert_or_assign (d_scores required for CUSTOM).
+ */
+int cskv_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values, const uint64_t* d_scores,
+                uint8_t* d_found, void* d_ws, size_t ws_bytes, void* stream);
+int cskv_assign_scores(cskv_table* table, uint64_t n, const uint64_t* d_keys, const uint64_t* d_scores,
+                       uint8_t* d_found, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * find_or_insert (inserter-group call of Sec. 3.5; Sec. 4.1's lookup with insertion for cold
+ * starts): insert_or_assign in which a resident key keeps its row (its score is updated as an
+ * UPDATE), absent keys are inserted with d_init_values under the same routing, admission and
+ * eviction rules (evicted entries are dropped).  d_values_out (n x dim fp32) receives, for every
+ * occurrence, the key's row from before the call if it was resident, else its last occurrence's
+ * init row (inserted or rejected alike; rows of reserved keys are left untouched).  d_status
+ * (nullable) as insert_or_assign.  d_ws: cskv_workspace_bytes(table, CSKV_OP_FIND_OR_INSERT, n)
+ * bytes.  Output rows must not alias the inputs.  Errors as insert_or_assign.
+ */
+int cskv_find_or_insert(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_init_values,
+                        const uint64_t* d_scores, float* d_values_out, uint8_t* d_status, void* d_ws, size_t ws_bytes,
+                        void* stream);
 
 /*
  * Launch-shape tuning (results never depend on it; the autotuner sets these):

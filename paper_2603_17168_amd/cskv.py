@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libcskv.so")
 
 MODE = {"single": 1, "dual": 2}
 POLICY = {"custom": 0, "lru": 1, "lfu": 2}
-OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE = 0, 1, 2, 3
+OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE, OP_ASSIGN, OP_FIND_OR_INSERT = 0, 1, 2, 3, 4, 5
 TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4, "find_pairs": 5}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
 
@@ -53,6 +53,12 @@ def lib():
         "cskv_erase": (I, [P, U64, P, P, P, SZ, P]),
         "cskv_size": (I, [P, P, P]),
         "cskv_export": (I, [P, U64, U64, P, P, P, P, P, P]),
+        "cskv_export_if": (I, [P, U64, U64, U64, P, P, P, P, P, P]),
+        "cskv_contains": (I, [P, U64, P, P, P]),
+        "cskv_find_ptr": (I, [P, U64, P, P, P, P, P]),
+        "cskv_assign": (I, [P, U64, P, P, P, P, P, SZ, P]),
+        "cskv_assign_scores": (I, [P, U64, P, P, P, P, SZ, P]),
+        "cskv_find_or_insert": (I, [P, U64, P, P, P, P, P, P, SZ, P]),
         "cskv_program_create": (I, [ctypes.POINTER(P), P]),
         "cskv_program_destroy": (I, [P]),
         "cskv_program_add_find": (I, [P, U64, P, P, P, P]),
@@ -237,6 +243,73 @@ class Table:
                                     _stream(self.device)), "cskv_erase")
         return erased_out
 
+    def contains(self, keys, found_out=None):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        if found_out is None:
+            found_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_contains(self._h, n, _ptr(keys), _ptr(found_out), _stream(self.device)), "cskv_contains")
+        return found_out
+
+    def find_ptr(self, keys, ptrs_out=None, found_out=None, scores_out=None):
+        """(device addresses of the resident rows as int64, 0 when absent; found; scores or None)."""
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        if ptrs_out is None:
+            ptrs_out = torch.empty(n, dtype=torch.int64, device=self.device)
+        if found_out is None:
+            found_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_find_ptr(self._h, n, _ptr(keys), _ptr(ptrs_out), _ptr(found_out), _ptr(scores_out),
+                                       _stream(self.device)), "cskv_find_ptr")
+        return ptrs_out, found_out, scores_out
+
+    def assign(self, keys, values, scores=None, found_out=None):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        values = self._vals(values, n)
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if found_out is None:
+            found_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(OP_ASSIGN, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_assign(self._h, n, _ptr(keys), _ptr(values), _ptr(scores), _ptr(found_out), _ptr(ws),
+                                     ws.numel(), _stream(self.device)), "cskv_assign")
+        return found_out
+
+    def assign_scores(self, keys, scores=None, found_out=None):
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if found_out is None:
+            found_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(OP_ASSIGN, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_assign_scores(self._h, n, _ptr(keys), _ptr(scores), _ptr(found_out), _ptr(ws),
+                                            ws.numel(), _stream(self.device)), "cskv_assign_scores")
+        return found_out
+
+    def find_or_insert(self, keys, init_values, scores=None, values_out=None, status_out=None):
+        """Returns (values_out [n, dim], status)."""
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        init_values = self._vals(init_values, n)
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if values_out is None:
+            values_out = torch.zeros((n, self.dim), dtype=torch.float32, device=self.device)
+        if status_out is None:
+            status_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(OP_FIND_OR_INSERT, n)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_find_or_insert(self._h, n, _ptr(keys), _ptr(init_values), _ptr(scores),
+                                             _ptr(values_out), _ptr(status_out), _ptr(ws), ws.numel(),
+                                             _stream(self.device)), "cskv_find_or_insert")
+        return values_out, status_out
+
     def size_tensor(self, out=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(1, dtype=torch.int64, device=self.device)
@@ -247,8 +320,10 @@ class Table:
     def size(self) -> int:
         return int(self.size_tensor().item())
 
-    def export(self, bucket_begin: int = 0, bucket_end: int | None = None, with_values: bool = True):
-        """(keys, values, scores, slots) of every entry in the bucket range (order unspecified)."""
+    def export(self, bucket_begin: int = 0, bucket_end: int | None = None, with_values: bool = True,
+               min_score: int = 0):
+        """(keys, values, scores, slots) of every entry in the bucket range (order unspecified);
+        with min_score > 0 only the entries whose score is at least min_score (export_if)."""
         b1 = self.n_buckets if bucket_end is None else bucket_end
         cap = max(1, (b1 - bucket_begin) * self.bucket_size)
         k = torch.empty(cap, dtype=torch.int64, device=self.device)
@@ -257,8 +332,12 @@ class Table:
         sl = torch.empty(cap, dtype=torch.int64, device=self.device)
         c = torch.zeros(1, dtype=torch.int64, device=self.device)
         with torch.cuda.device(self.device):
-            _check(lib().cskv_export(self._h, bucket_begin, b1, _ptr(k), _ptr(v), _ptr(s), _ptr(sl), _ptr(c),
-                                     _stream(self.device)), "cskv_export")
+            if min_score:
+                _check(lib().cskv_export_if(self._h, bucket_begin, b1, int(min_score), _ptr(k), _ptr(v), _ptr(s),
+                                            _ptr(sl), _ptr(c), _stream(self.device)), "cskv_export_if")
+            else:
+                _check(lib().cskv_export(self._h, bucket_begin, b1, _ptr(k), _ptr(v), _ptr(s), _ptr(sl), _ptr(c),
+                                         _stream(self.device)), "cskv_export")
         n = int(c.item())
         return k[:n], (v[:n] if v is not None else None), s[:n], sl[:n]
 

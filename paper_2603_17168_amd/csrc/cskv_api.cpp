@@ -163,7 +163,9 @@ size_t cskv_workspace_bytes(const cskv_table* table, int op, uint64_t n) {
     switch (op) {
         case CSKV_OP_FIND: return 0;
         case CSKV_OP_INSERT_OR_ASSIGN:
-        case CSKV_OP_INSERT_AND_EVICT: return upsert_layout(n, table->view.nbuckets).total;
+        case CSKV_OP_INSERT_AND_EVICT:
+        case CSKV_OP_ASSIGN:
+        case CSKV_OP_FIND_OR_INSERT: return upsert_layout(n, table->view.nbuckets).total;
         case CSKV_OP_ERASE: return erase_ws_bytes(n);
         default: return 0;
     }
@@ -187,13 +189,14 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
 namespace cskv {
 
 int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, UpsertWs* out,
-                size_t* zero_out) {
+                size_t* zero_out, bool need_vals) {
     const uint64_t n = a.n;
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
-    if (!a.keys || !a.vals || !d_ws) return CSKV_EINVAL;
+    if (!a.keys || (need_vals && !a.vals) || !d_ws) return CSKV_EINVAL;
     if (table->policy == CSKV_SCORE_CUSTOM && !a.scores) return CSKV_EINVAL;
-    if (!aligned(a.keys, 8) || !aligned(a.vals, 16) || !aligned(d_ws, 256) || (a.scores && !aligned(a.scores, 8)))
+    if (!aligned(a.keys, 8) || (a.vals && !aligned(a.vals, 16)) || !aligned(d_ws, 256) ||
+        (a.scores && !aligned(a.scores, 8)) || (a.out && !aligned(a.out, 16)))
         return CSKV_EINVAL;
     const UpsertLayout L = upsert_layout(n, table->view.nbuckets);
     if (ws_bytes < L.total) return CSKV_ENOMEM;
@@ -214,6 +217,7 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     w.logP = L.logP;
     w.cap = L.cap;
     w.list_mode = L.list_mode;
+    w.out = a.out;
     *zero_out = table->policy == CSKV_SCORE_LFU ? L.off_zero_end_lfu : L.off_zero_end;
     return CSKV_OK;
 }
@@ -278,7 +282,71 @@ int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, u
         (d_scores && !aligned(d_scores, 8)) || (d_slots && !aligned(d_slots, 8)))
         return CSKV_EINVAL;
     return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
-                                as_stream(stream)));
+                                0, as_stream(stream)));
+}
+
+int cskv_export_if(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, uint64_t min_score,
+                   uint64_t* d_keys, float* d_values, uint64_t* d_scores, uint64_t* d_slots, uint64_t* d_count,
+                   void* stream) {
+    if (!table || !d_keys || !d_count) return CSKV_EINVAL;
+    if (bucket_begin > bucket_end || bucket_end > table->view.nbuckets) return CSKV_EINVAL;
+    if (!aligned(d_keys, 8) || !aligned(d_count, 8) || (d_values && !aligned(d_values, 16)) ||
+        (d_scores && !aligned(d_scores, 8)) || (d_slots && !aligned(d_slots, 8)))
+        return CSKV_EINVAL;
+    return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
+                                min_score, as_stream(stream)));
+}
+
+int cskv_contains(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_found, void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_found || !aligned(d_keys, 8)) return CSKV_EINVAL;
+    return hip_rc(launch_locate(table->view, n, d_keys, d_found, nullptr, nullptr, table->group, as_stream(stream)));
+}
+
+int cskv_find_ptr(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint64_t* d_ptrs, uint8_t* d_found,
+                  uint64_t* d_scores_out, void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    if (!d_keys || !d_ptrs || !d_found || !aligned(d_keys, 8) || !aligned(d_ptrs, 8) ||
+        (d_scores_out && !aligned(d_scores_out, 8)))
+        return CSKV_EINVAL;
+    return hip_rc(launch_locate(table->view, n, d_keys, d_found, d_ptrs, d_scores_out, table->group, as_stream(stream)));
+}
+
+static int enqueue_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                          const uint64_t* d_scores, uint8_t* d_found, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!table || !n_ok(n)) return CSKV_EINVAL;
+    if (n == 0) return CSKV_OK;
+    UpsertArgs a{n, d_keys, d_values, d_scores, nullptr, EvictOut{nullptr, nullptr, nullptr, nullptr}};
+    UpsertWs w;
+    size_t zero_bytes = 0;
+    const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes, false);
+    if (rc != CSKV_OK) return rc;
+    hipStream_t s = as_stream(stream);
+    const hipError_t e = launch_upsert_prep(table->view, w, n, d_keys, d_scores, a.ev, zero_bytes, s);
+    if (e != hipSuccess) return CSKV_EHIP;
+    return hip_rc(launch_assign(table->view, w, n, d_keys, d_values, d_scores, d_found, table->group, s));
+}
+
+int cskv_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values, const uint64_t* d_scores,
+                uint8_t* d_found, void* d_ws, size_t ws_bytes, void* stream) {
+    if (n && !d_values) return CSKV_EINVAL;
+    return enqueue_assign(table, n, d_keys, d_values, d_scores, d_found, d_ws, ws_bytes, stream);
+}
+
+int cskv_assign_scores(cskv_table* table, uint64_t n, const uint64_t* d_keys, const uint64_t* d_scores,
+                       uint8_t* d_found, void* d_ws, size_t ws_bytes, void* stream) {
+    return enqueue_assign(table, n, d_keys, nullptr, d_scores, d_found, d_ws, ws_bytes, stream);
+}
+
+int cskv_find_or_insert(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_init_values,
+                        const uint64_t* d_scores, float* d_values_out, uint8_t* d_status, void* d_ws, size_t ws_bytes,
+                        void* stream) {
+    if (n && (!d_init_values || !d_values_out)) return CSKV_EINVAL;
+    UpsertArgs a{n, d_keys, d_init_values, d_scores, d_status, EvictOut{nullptr, nullptr, nullptr, nullptr}};
+    a.out = d_values_out;
+    return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_set_tuning(cskv_table* table, int param, int value) {

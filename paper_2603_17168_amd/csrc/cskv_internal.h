@@ -79,6 +79,7 @@ struct UpsertWs {
     int logP;
     uint32_t cap;    // inline operations per bucket
     int list_mode;   // apply visits only the touched buckets (small batches)
+    float* out;      // find_or_insert: rows returned per occurrence (resident rows are kept); else null
 };
 
 // one batch of a merged run of finds (reader group): keys [begin, begin + n) of the run
@@ -145,13 +146,18 @@ hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n
                                const uint64_t* scores, int group, hipStream_t s);
 hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals,
                                const EvictOut& ev, hipStream_t s);
-hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s);
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, uint32_t dim, hipStream_t s);
 hipError_t launch_erase_probe(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                               uint32_t* ws_slot, int group, hipStream_t s);
 hipError_t launch_erase_clear(const TableView& t, uint64_t n, uint32_t* ws_slot, hipStream_t s);
 hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s);
 hipError_t launch_export(const TableView& t, uint64_t b0, uint64_t b1, uint64_t* keys, float* vals,
-                         uint64_t* scores, uint64_t* slots, uint64_t* count, hipStream_t s);
+                         uint64_t* scores, uint64_t* slots, uint64_t* count, uint64_t min_score, hipStream_t s);
+// contains (ptrs null) / find_ptr; assign / assign_scores (vals null) after the dedupe pass
+hipError_t launch_locate(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* found, uint64_t* ptrs,
+                         uint64_t* scores, int group, hipStream_t s);
+hipError_t launch_assign(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
+                         const uint64_t* scores, uint8_t* found, int group, hipStream_t s);
 
 // enqueue helpers shared by the single-call C ABI and the batched program (return CSKV_* codes)
 struct UpsertArgs {
@@ -161,6 +167,7 @@ struct UpsertArgs {
     const uint64_t* scores;
     uint8_t* status;
     EvictOut ev;
+    float* out = nullptr;  // find_or_insert: returned rows (resident rows are kept, not replaced)
 };
 
 }  // namespace cskv
@@ -181,7 +188,8 @@ struct cskv_table {
 
 namespace cskv {
 // validates an upsert and lays out its workspace (CSKV_* code)
-int plan_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, UpsertWs* w, size_t* zero_bytes);
+int plan_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, UpsertWs* w, size_t* zero_bytes,
+                bool need_vals = true);
 int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
 int enqueue_erase(cskv_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased, void* ws, size_t ws_bytes,
                   hipStream_t s);

@@ -138,13 +138,18 @@ hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s) {
 // export: one wave per bucket; output positions from one atomic per bucket
 __global__ void __launch_bounds__(64) k_export(TableView t, uint64_t b0, uint64_t b1, uint64_t* __restrict__ keys,
                                                float* __restrict__ vals, uint64_t* __restrict__ scores,
-                                               uint64_t* __restrict__ slots, uint64_t* __restrict__ count) {
+                                               uint64_t* __restrict__ slots, uint64_t* __restrict__ count,
+                                               uint64_t min_score) {
     __shared__ unsigned long long base_s;
     __shared__ uint8_t sl[128];
     const int lane = threadIdx.x;
     for (uint64_t b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
         const size_t eb = (size_t)b * kSlots;
-        const bool o0 = t.dig[eb + lane] != 0, o1 = t.dig[eb + lane + 64] != 0;
+        bool o0 = t.dig[eb + lane] != 0, o1 = t.dig[eb + lane + 64] != 0;
+        if (min_score) {  // export_batch_if: entries whose score is at least min_score
+            o0 = o0 && t.scores[eb + lane] >= min_score;
+            o1 = o1 && t.scores[eb + lane + 64] >= min_score;
+        }
         const uint64_t bal0 = __ballot(o0), bal1 = __ballot(o1);
         const int c = __popcll(bal0) + __popcll(bal1);
         const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -172,12 +177,12 @@ __global__ void __launch_bounds__(64) k_export(TableView t, uint64_t b0, uint64_
 }
 
 hipError_t launch_export(const TableView& t, uint64_t b0, uint64_t b1, uint64_t* keys, float* vals,
-                         uint64_t* scores, uint64_t* slots, uint64_t* count, hipStream_t s) {
+                         uint64_t* scores, uint64_t* slots, uint64_t* count, uint64_t min_score, hipStream_t s) {
     hipError_t e = launch_fill_zero(count, 8, s);
     if (e != hipSuccess || b1 <= b0) return e;
     uint64_t blocks = b1 - b0;
     if (blocks > 65536) blocks = 65536;
-    k_export<<<(unsigned)blocks, 64, 0, s>>>(t, b0, b1, keys, vals, scores, slots, count);
+    k_export<<<(unsigned)blocks, 64, 0, s>>>(t, b0, b1, keys, vals, scores, slots, count, min_score);
     return hipGetLastError();
 }
 

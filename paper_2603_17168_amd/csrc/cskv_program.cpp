@@ -463,7 +463,7 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
         case kPhPrep: e = launch_upsert_prep(t->view, w, a.n, a.keys, a.scores, a.ev, zero_bytes, s); break;
         case kPhRoute: e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, t->route_group, s); break;
         case kPhApply: e = launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s); break;
-        default: e = launch_upsert_finish(w, a.n, a.status, s); break;
+        default: e = launch_upsert_finish(w, a.n, a.status, t->view.dim, s); break;
     }
     return e == hipSuccess ? CSKV_OK : CSKV_EHIP;
 }

@@ -357,15 +357,30 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             }
         }
     }
-    // rows: chunk c of every row by lane c mod 16; updates before evictions
+    // rows: chunk c of every row by lane c mod 16; updates before evictions.  find_or_insert
+    // (w.out set) keeps a resident row and returns it; every insert returns its own row.
     const uint32_t chunks = t.dim >> 2;
     for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
         const int x = __ffs(ub) - 1;
         const int us = __shfl((int)e.slot, x, GA);
         const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
         uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
-        const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
-        for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+        if (w.out) {
+            uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) o[c] = dst[c];
+        } else {
+            const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
+        }
+    }
+    if (w.out) {
+        for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
+            const int x = __ffs(ib) - 1;
+            const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+            uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
+            const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) o[c] = src[c];
+        }
     }
     for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
         const int x = __ffs(ib) - 1;
@@ -466,10 +481,24 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                 const int us = __shfl((int)e.slot, x);
                 const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x);
                 uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
-                const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
-                for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
+                if (w.out) {  // find_or_insert: the resident row stays and is returned
+                    uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
+                    for (uint32_t c = lane; c < chunks; c += 64) o[c] = dst[c];
+                } else {
+                    const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+                    for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
+                }
             }
             const uint64_t ib = __ballot(ins);
+            if (w.out) {  // find_or_insert: every insert returns its own row
+                for (uint64_t q = ib; q; q &= q - 1) {
+                    const int x = __ffsll((unsigned long long)q) - 1;
+                    const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x);
+                    uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
+                    const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+                    for (uint32_t c = lane; c < chunks; c += 64) o[c] = src[c];
+                }
+            }
             const int cn = __popcll(ib);
             if (ins) {
                 const int at = nbest + __popcll(ib & below);
@@ -642,11 +671,20 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
 }
 
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t* __restrict__ status) {
+__global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t* __restrict__ status, uint32_t dim) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t p = w.slot_of[i];
-    status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
+    if (status) status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
+    if (w.out && p != kNoSlot) {  // find_or_insert: a repeated key returns its last occurrence's row
+        const DedupeEntry de = w.dd[p];
+        const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
+        if (last != (uint32_t)i) {
+            const uint4* src = reinterpret_cast<const uint4*>(w.out + (size_t)last * dim);
+            uint4* dst = reinterpret_cast<uint4*>(w.out + i * dim);
+            for (uint32_t c = 0; c < (dim >> 2); ++c) dst[c] = src[c];
+        }
+    }
 }
 
 template <int G>
@@ -686,9 +724,9 @@ hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n
     return hipGetLastError();
 }
 
-hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, hipStream_t s) {
-    if (n == 0 || !status) return hipSuccess;
-    k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status);
+hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, uint32_t dim, hipStream_t s) {
+    if (n == 0 || (!status && !w.out)) return hipSuccess;
+    k_finish<<<blocks_for(n, 256), 256, 0, s>>>(w, n, status, dim);
     return hipGetLastError();
 }
 
@@ -699,7 +737,7 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
     if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
     if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
     if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
-    return launch_upsert_finish(w, n, status, s);
+    return launch_upsert_finish(w, n, status, t.dim, s);
 }
 
 }  // namespace cskv

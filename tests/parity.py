@@ -106,6 +106,96 @@ class Twin:
         assert np.array_equal(er.cpu().numpy(), oer), "erased flags differ"
         return oer
 
+    def _scores_arg(self, scores):
+        return None if scores is None else from_u64(np.asarray(scores, dtype=np.uint64), self.device)
+
+    def contains(self, keys: np.ndarray):
+        keys = np.asarray(keys, dtype=np.uint64)
+        f = self.gpu.contains(from_u64(keys, self.device))
+        of = self.ora.contains(keys)
+        torch.cuda.synchronize()
+        assert np.array_equal(f.cpu().numpy(), of), "contains flags differ"
+        return of
+
+    def find_ptr(self, keys: np.ndarray):
+        """Pointers must address the resident row: one base for all, each slot in the oracle's
+        bucket for the key, rows equal (via the slot -> row map of the exported table)."""
+        keys = np.asarray(keys, dtype=np.uint64)
+        sc = torch.empty(keys.size, dtype=torch.int64, device=self.device)
+        ptr, f, sc = self.gpu.find_ptr(from_u64(keys, self.device), scores_out=sc)
+        of, ob = self.ora.locate(keys)
+        _, _, osc = self.ora.find(keys)
+        torch.cuda.synchronize()
+        assert np.array_equal(f.cpu().numpy(), of), "find_ptr flags differ"
+        gp = as_u64(ptr)
+        hit = np.nonzero(of)[0]
+        assert np.all(gp[of == 0] == 0), "absent keys got a pointer"
+        if hit.size == 0:
+            return of
+        gk, gv, gs, gsl = self.gpu.export()
+        slot_of = dict(zip(as_u64(gk).tolist(), as_u64(gsl).tolist()))
+        row_of = {int(sl): i for i, sl in enumerate(as_u64(gsl).tolist())}
+        rb = self.dim * 4
+        i0 = hit[0]
+        base = int(gp[i0]) - slot_of[int(keys[i0])] * rb
+        for i in hit:
+            sl = slot_of[int(keys[i])]
+            assert int(gp[i]) == base + sl * rb, "pointer does not address the key's slot"
+            assert sl // 128 == int(ob[i]), "pointer outside the key's bucket"
+        assert np.array_equal(as_u64(sc.cpu())[hit], osc[hit]), "find_ptr scores differ"
+        return of
+
+    def assign(self, keys: np.ndarray, scores=None, with_values: bool = True):
+        keys = np.asarray(keys, dtype=np.uint64)
+        kd = from_u64(keys, self.device)
+        if with_values:
+            vids = self._vids(keys.size)
+            f = self.gpu.assign(kd, self.rows(vids).to(self.device), self._scores_arg(scores))
+            of = self.ora.assign(keys, vids, scores)
+        else:
+            f = self.gpu.assign_scores(kd, self._scores_arg(scores))
+            of = self.ora.assign(keys, None, scores)
+        torch.cuda.synchronize()
+        assert np.array_equal(f.cpu().numpy(), of), "assign flags differ"
+        assert self.gpu.clock == self.ora.clock
+        return of
+
+    def find_or_insert(self, keys: np.ndarray, scores=None):
+        keys = np.asarray(keys, dtype=np.uint64)
+        n = keys.size
+        vids = self._vids(n)
+        out = torch.full((n, self.dim), 0, dtype=torch.int32, device=self.device)
+        out.fill_(NAN_BITS)
+        out = out.view(torch.float32)
+        vals, st = self.gpu.find_or_insert(from_u64(keys, self.device), self.rows(vids).to(self.device),
+                                           self._scores_arg(scores), values_out=out)
+        ost, ovid = self.ora.find_or_insert(keys, vids, scores)
+        torch.cuda.synchronize()
+        gst = st.cpu().numpy()
+        if not np.array_equal(gst, ost):
+            bad = np.nonzero(gst != ost)[0]
+            raise AssertionError(f"find_or_insert status mismatch at {bad[:10]}: gpu {gst[bad[:10]]} oracle {ost[bad[:10]]}")
+        valid = np.nonzero(ost != oracle.INVALID_KEY)[0]
+        bad_rows = np.nonzero(ost == oracle.INVALID_KEY)[0]
+        gv = bits(vals.cpu())
+        if valid.size:
+            assert torch.equal(gv[torch.from_numpy(valid)], bits(self.rows(ovid[valid]))), "find_or_insert rows differ"
+        if bad_rows.size:
+            assert bool((gv[torch.from_numpy(bad_rows)] == NAN_BITS).all()), "rows of reserved keys were written"
+        assert self.gpu.clock == self.ora.clock
+        return ost
+
+    def export_if(self, min_score: int):
+        gk, gv, gs, gsl = self.gpu.export(min_score=min_score)
+        ok, ov, os_, ob = self.ora.export_if(min_score)
+        torch.cuda.synchronize()
+        gk = as_u64(gk)
+        assert gk.size == ok.size, f"export_if count gpu {gk.size} oracle {ok.size}"
+        go, oo = np.argsort(gk, kind="stable"), np.argsort(ok, kind="stable")
+        assert np.array_equal(gk[go], ok[oo]) and np.array_equal(as_u64(gs)[go], os_[oo])
+        if gk.size:
+            assert torch.equal(bits(gv.cpu()[torch.from_numpy(go)]), bits(self.rows(ov[oo]))), "export_if rows differ"
+
     # ------------------------------------------------------------------ whole-table check
     def check_table(self, with_values: bool = True):
         gk, gv, gs, gsl = self.gpu.export(with_values=with_values)
