@@ -463,6 +463,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--no-api", action="store_true", help="skip the contains / find_ptr / assign / find_or_insert rates")
     ap.add_argument("--counter-probe", action="store_true",
                     help="run only the short fixed call sequence used for hardware-counter runs")
     args = ap.parse_args()
@@ -576,6 +577,44 @@ def main():
         torch.cuda.synchronize()
         cold[li] = batch / e0.elapsed_time(e1) / 1e6
     del scrub
+    # the rest of the API (not in `value`): median of 3 event-timed calls per load
+    api = {}
+    if not args.no_api:
+        ptrs = torch.empty(batch, dtype=torch.int64, device=dev)
+        fo_rows = torch.empty((batch, dim), dtype=torch.float32, device=dev)
+
+        def timed(fn, reps=3):
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            return batch / float(np.median(ms)) / 1e6
+
+        for li, lv in enumerate(levels):
+            t = lv.t
+            r = {"contains_hit100_bkvs": timed(lambda: t.contains(q100[li], found_out=found)),
+                 "contains_hit50_bkvs": timed(lambda: t.contains(q50[li], found_out=found)),
+                 "find_ptr_hit100_bkvs": timed(lambda: t.find_ptr(q100[li], ptrs_out=ptrs, found_out=found)),
+                 "assign_bkvs": timed(lambda: t.assign(q100[li], rows, found_out=found)),
+                 "assign_scores_bkvs": timed(lambda: t.assign_scores(q100[li], found_out=found))}
+            # find_or_insert of half resident, half fresh keys; the fresh ones are erased again
+            fk = torch.cat([q100[li][: batch // 2], gen_keys(850 + li, batch - batch // 2, 0, device=dev)])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t.find_or_insert(fk, rows, values_out=fo_rows, status_out=status)
+            e1.record()
+            torch.cuda.synchronize()
+            r["find_or_insert_half_resident_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
+            if lv.target < 1.0:
+                t.erase(fk[batch // 2:], erased_out=erased)
+            api[f"{lv.target:.2f}"] = {k: round(v, 3) for k, v in r.items()}
+        torch.cuda.synchronize()
+        log(f"api: {api}")
+
     # status histogram of one more fresh-key insert_or_assign per load (then erased again)
     hists = {}
     for li, lv in enumerate(levels):
@@ -645,6 +684,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_find (autotuned per load, see tuning)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": find_traffic_per_launch(dim, [lv.target for lv in levels], batch)},
+        "api": api,
         "roofline_upsert": {"bound": "hbm", "kernel": "insert_or_assign (every kernel of one call)",
                             "achieved": round(ups_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(ups_achieved / HBM_PEAK_GBS, 4), "traffic": None,
