@@ -229,10 +229,11 @@ def autotune(t, q100, q50, fresh, rows, outs, found, status, erased, reps=3, tun
 
 
 def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, hi=1 << 20):
-    """Batched programs: 256 uneven batches (log-uniform 1K..1M keys, 70/25/5 find / upsert /
-    erase) on a 2^26-slot dim-32 LRU table prefilled to load 0.9, run three ways from the same
-    starting table: plain per-batch calls, one program launch (merged reader runs, autotuned
-    shapes per size class), and the program captured as a hipGraph and replayed."""
+    """Batched programs: 256 uneven batches (log-uniform lo..hi keys, default 1K..1M; 70/25/5
+    find / upsert / erase) on a 2^26-slot dim-32 LRU table prefilled to load 0.9, run from the
+    same starting table as plain per-batch calls, as one program launch (merged reader runs,
+    autotuned shapes per size class) and as the program captured as a hipGraph and replayed, in
+    the single-stream and the overlapped forms."""
     cap = 1 << log2_cap
     base = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
     offered, size = fill(base, load, 1 << 20, dim, 2, 0, dev)
@@ -294,8 +295,8 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
 
     same = True
     prog = None
-    for overlap in (False, True):
-        tag = "_overlapped" if overlap else ""
+    for overlap in (0, 1, 2):
+        tag = {0: "", 1: "_overlapped", 2: "_prep_ahead"}[overlap]
         prog = build(overlap)
         res["program" + tag] = best_of(prog.launch, torch.cuda.synchronize)
         same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
@@ -314,6 +315,8 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
            "graph_bkvs": round(total / res["graph"] / 1e9, 3),
            "program_overlapped_bkvs": round(total / res["program_overlapped"] / 1e9, 3),
            "graph_overlapped_bkvs": round(total / res["graph_overlapped"] / 1e9, 3),
+           "program_prep_ahead_bkvs": round(total / res["program_prep_ahead"] / 1e9, 3),
+           "graph_prep_ahead_bkvs": round(total / res["graph_prep_ahead"] / 1e9, 3),
            "graph_vs_plain": round(res["plain_s"] / res["graph"], 3),
            "identical_outputs": bool(same), "tuning": tuning}
     del prog, base, snap, ops
@@ -701,6 +704,8 @@ def main():
     if not args.no_batched:
         log("batched programs")
         out["batched"] = bench_batched(dev)
+        log("batched programs, small batches")
+        out["batched_small"] = bench_batched(dev, lo=1 << 10, hi=1 << 14)
     if not args.no_serving:
         log("serving loop")
         out["serving"] = bench_serving(dev, nreq=args.serve_requests)

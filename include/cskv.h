@@ -299,10 +299,13 @@ int cskv_program_add_erase(cskv_program* prog, uint64_t n, const uint64_t* d_key
  * back into the launch stream; cskv_program_capture builds a hipGraph with one child node per
  * phase (each recorded alone on `stream`) and the dependencies as edges.  Independent phases of
  * different batches then overlap on the device, at the price of cross-stream event waits.
+ * 2: prep ahead: the same graph with every phase but the scratch preparations chained in program
+ * order on one stream, so that only each upsert's clear and dedupe run ahead, beside earlier
+ * batches (two cross-stream waits per upsert).
  * 0 (default): every phase in program order on the launch stream (the captured graph is that one
- * sequence).  Set before cskv_program_set_workspace.
+ * sequence).  Set before cskv_program_set_workspace; CSKV_EINVAL for another mode.
  */
-int cskv_program_set_overlap(cskv_program* prog, int enabled);
+int cskv_program_set_overlap(cskv_program* prog, int mode);
 size_t cskv_program_workspace_bytes(const cskv_program* prog);
 int cskv_program_set_workspace(cskv_program* prog, void* d_ws, size_t ws_bytes);
 /* number of kernel-sequence segments: merged find runs + upserts + erases */

@@ -347,7 +347,9 @@ class Program:
     run; upserts and erases are serialization points; the whole program can be captured once as a
     hipGraph and replayed.  Tensors passed to add_* are kept alive by the program."""
 
-    def __init__(self, table: Table, overlap: bool = False):
+    def __init__(self, table: Table, overlap=False):
+        """overlap: False / 0 (one stream), True / 1 (phase graph on several streams) or 2 (only
+        each upsert's scratch preparation runs ahead on a side stream)."""
         self.table = table
         h = ctypes.c_void_p()
         _check(lib().cskv_program_create(ctypes.byref(h), table._h), "cskv_program_create")

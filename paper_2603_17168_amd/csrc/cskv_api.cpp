@@ -62,7 +62,7 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
     L.off_touched = o; o = align256(o + nslow * 4);
-    L.list_mode = n * 32 <= nb;  // a small batch: apply visits only the touched buckets
+    L.list_mode = n * 4 <= nb;  // apply visits only the touched buckets (route lists them)
     L.total = o;
     return L;
 }

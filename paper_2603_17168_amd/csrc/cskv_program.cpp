@@ -84,7 +84,7 @@ struct cskv_program {
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraph_t> children;  // per-phase graphs of the overlapped form's graph
     bool ready = false;
-    bool overlap = false;
+    int overlap = 0;  // 0: one stream; 1: phase graph on reader / writer / prep streams; 2: prep ahead
     hipStream_t lane[kLanes] = {};
     std::vector<hipEvent_t> events;  // one per phase, then the fork event
 };
@@ -238,6 +238,20 @@ static void build_phases(cskv_program* p) {
         slot_free[j] = end;
         seg_end[s] = end;
     }
+    // prep ahead: every phase but the scratch preparations runs in program order on one stream
+    if (p->overlap == 2) {
+        int prev = -1;
+        for (uint32_t i = 0; i < p->phases.size(); ++i) {
+            Phase& ph = p->phases[i];
+            if (ph.kind == kPhPrep) continue;
+            ph.lane = kLaneWrite;
+            if (prev >= 0 && std::find(ph.deps.begin(), ph.deps.end(), (uint32_t)prev) == ph.deps.end()) {
+                ph.deps.push_back((uint32_t)prev);  // explicit in the graph form; stream order in the event form
+                std::sort(ph.deps.begin(), ph.deps.end());
+            }
+            prev = (int)i;
+        }
+    }
     // a phase signals when a phase on another lane waits for it, or when it is its lane's last
     int lane_last[kLanes];
     std::fill(lane_last, lane_last + kLanes, -1);
@@ -294,9 +308,9 @@ int cskv_program_destroy(cskv_program* p) {
     return CSKV_OK;
 }
 
-int cskv_program_set_overlap(cskv_program* p, int enabled) {
-    if (!p || p->ready) return CSKV_EINVAL;
-    p->overlap = enabled != 0;
+int cskv_program_set_overlap(cskv_program* p, int mode) {
+    if (!p || p->ready || mode < 0 || mode > 2) return CSKV_EINVAL;
+    p->overlap = mode;
     return CSKV_OK;
 }
 

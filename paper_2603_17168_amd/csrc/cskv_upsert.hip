@@ -157,7 +157,18 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     }
     if (lane == 0) {
         const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
-        if (w.list_mode && r == 0) w.touched[atomicAdd(w.ctr + kCtrTouched, 1u)] = tgt;
+        if (w.list_mode) {  // newly touched buckets: one cursor atomic per wave, not per bucket
+            const bool first = r == 0;
+            const uint64_t bal = __ballot(first);  // over the active group leaders of this wave
+            if (bal) {
+                const int me = threadIdx.x & 63;
+                const int leader = __ffsll((unsigned long long)bal) - 1;
+                uint32_t base = 0;
+                if (me == leader) base = atomicAdd(w.ctr + kCtrTouched, (uint32_t)__popcll(bal));
+                base = (uint32_t)__shfl((int)base, leader);
+                if (first) w.touched[base + __popcll(bal & ((1ull << me) - 1))] = tgt;
+            }
+        }
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         if (r < w.cap) {
             store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot);
