@@ -604,6 +604,17 @@ def main():
                  "find_ptr_hit100_bkvs": timed(lambda: t.find_ptr(q100[li], ptrs_out=ptrs, found_out=found)),
                  "assign_bkvs": timed(lambda: t.assign(q100[li], rows, found_out=found)),
                  "assign_scores_bkvs": timed(lambda: t.assign_scores(q100[li], found_out=found))}
+            # digest ablation (Exp. 3a): the same find calls without the digest filter (best lane
+            # group of the ablated kernel)
+            tu = t.get_tuning()
+            for h, q in (("100", q100[li]), ("50", q50[li])):
+                r[f"find_hit{h}_bkvs"] = timed(lambda: t.find(q, values_out=outs, found_out=found, want_scores=False))
+                best = 0.0
+                for g in (4, 8, 16):
+                    t.set_tuning(find_digest=0, find_group=g)
+                    best = max(best, timed(lambda: t.find(q, values_out=outs, found_out=found, want_scores=False)))
+                r[f"find_nodigest_hit{h}_bkvs"] = best
+                t.set_tuning(find_digest=1, find_group=tu["find_group"])
             # find_or_insert of half resident, half fresh keys; the fresh ones are erased again
             fk = torch.cat([q100[li][: batch // 2], gen_keys(850 + li, batch - batch // 2, 0, device=dev)])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

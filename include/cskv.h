@@ -234,6 +234,10 @@ int cskv_find_or_insert(cskv_table* table, uint64_t n, const uint64_t* d_keys, c
  *                              compute unit striding over the run's keys
  *  CSKV_TUNE_FIND_PAIRS        1 = cskv_find serves two keys per lane group with their loads
  *                              interleaved, 0 = one key per group (default)
+ *  CSKV_TUNE_FIND_DIGEST       1 = cskv_find filters candidate slots by the digest line (Alg. 1,
+ *                              default); 0 = the digest ablation of Exp. 3a: every probe compares
+ *                              the key with all 128 stored keys of the bucket (1 KiB instead of
+ *                              the 128-byte digest line).  Programs and the server always filter.
  * cskv_set_tuning returns CSKV_EINVAL for an unknown parameter or value; cskv_get_tuning returns
  * the current value, or -1.
  */
@@ -242,7 +246,8 @@ enum {
     CSKV_TUNE_ROUTE_GROUP = 2,
     CSKV_TUNE_FIND_PREFETCH_B2 = 3,
     CSKV_TUNE_FIND_BLOCKS_PER_CU = 4,
-    CSKV_TUNE_FIND_PAIRS = 5
+    CSKV_TUNE_FIND_PAIRS = 5,
+    CSKV_TUNE_FIND_DIGEST = 6
 };
 int cskv_set_tuning(cskv_table* table, int param, int value);
 int cskv_get_tuning(const cskv_table* table, int param);

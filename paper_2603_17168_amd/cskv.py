@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcskv.so")
 MODE = {"single": 1, "dual": 2}
 POLICY = {"custom": 0, "lru": 1, "lfu": 2}
 OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE, OP_ASSIGN, OP_FIND_OR_INSERT = 0, 1, 2, 3, 4, 5
-TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4, "find_pairs": 5}
+TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4, "find_pairs": 5, "find_digest": 6}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
 
 _lib = None

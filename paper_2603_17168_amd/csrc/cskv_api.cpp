@@ -132,6 +132,7 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->prefetch_b2 = 0;
     t->blocks_per_cu = 0;
     t->find_pairs = 0;
+    t->find_digest = 1;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         delete t;
@@ -180,6 +181,9 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
     if (!d_keys || !d_values_out || !d_found) return CSKV_EINVAL;
     if (!aligned(d_keys, 8) || !aligned(d_values_out, 16) || (d_scores_out && !aligned(d_scores_out, 8)))
         return CSKV_EINVAL;
+    if (!table->find_digest)
+        return hip_rc(launch_find_nodigest(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
+                                           as_stream(stream)));
     return hip_rc(launch_find(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
                               table->prefetch_b2, table->find_pairs, as_stream(stream)));
 }
@@ -372,6 +376,10 @@ int cskv_set_tuning(cskv_table* table, int param, int value) {
             if (value != 0 && value != 1) return CSKV_EINVAL;
             table->find_pairs = value;
             return CSKV_OK;
+        case CSKV_TUNE_FIND_DIGEST:
+            if (value != 0 && value != 1) return CSKV_EINVAL;
+            table->find_digest = value;
+            return CSKV_OK;
         default: return CSKV_EINVAL;
     }
 }
@@ -384,6 +392,7 @@ int cskv_get_tuning(const cskv_table* table, int param) {
         case CSKV_TUNE_FIND_PREFETCH_B2: return table->prefetch_b2;
         case CSKV_TUNE_FIND_BLOCKS_PER_CU: return table->blocks_per_cu;
         case CSKV_TUNE_FIND_PAIRS: return table->find_pairs;
+        case CSKV_TUNE_FIND_DIGEST: return table->find_digest;
         default: return -1;
     }
 }

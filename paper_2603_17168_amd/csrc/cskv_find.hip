@@ -196,6 +196,73 @@ __global__ void __launch_bounds__(256) k_find_args(TableView t, FindDescArgs a) 
     find_one<G, PRE>(t, q.keys[i], q.out + i * t.dim, q.found + i, q.scores ? q.scores + i : nullptr, glane<G>());
 }
 
+// ------------------------------------------------------------------------------------------
+// digest ablation (Exp. 3a): the same lookup with no digest filter.  The group compares the key
+// with all 128 stored keys of each candidate bucket (1 KiB); at step j lane l reads slots
+// 2(jG + l) and 2(jG + l) + 1, so each load instruction of a group covers one contiguous
+// 16G-byte run.  A matching slot still has its digest byte read, because a freed slot keeps its
+// stale key.
+template <int G>
+__device__ __forceinline__ int scan_keys(const TableView& t, uint32_t b, uint64_t k, int lane) {
+    constexpr int STEPS = kSlots / (2 * G);
+    const size_t eb = (size_t)b * kSlots;
+    const ulonglong2* bk = reinterpret_cast<const ulonglong2*>(t.keys + eb);
+    ulonglong2 x[STEPS];
+#pragma unroll
+    for (int j = 0; j < STEPS; ++j) x[j] = bk[j * G + lane];
+    int hit = -1;
+#pragma unroll
+    for (int j = 0; j < STEPS; ++j) {
+        const int s0 = 2 * (j * G + lane);
+        if (x[j].x == k && hit < 0 && t.dig[eb + s0] != 0) hit = s0;
+        if (x[j].y == k && hit < 0 && t.dig[eb + s0 + 1] != 0) hit = s0 + 1;
+    }
+    return gmax_i<G>(hit);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_find_nodigest(TableView t, uint64_t n, const uint64_t* __restrict__ keys,
+                                                       float* __restrict__ out, uint8_t* __restrict__ found,
+                                                       uint64_t* __restrict__ scores_out) {
+    const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= n) return;
+    const int lane = glane<G>();
+    const uint64_t k = keys[i];
+    int slot = -1;
+    uint32_t b = 0;
+    if (!reserved_key(k)) {
+        const KeyHash h = hash_key(t, k);
+        b = h.b1;
+        slot = scan_keys<G>(t, h.b1, k, lane);
+        if (slot < 0 && h.b2 != h.b1) {
+            b = h.b2;
+            slot = scan_keys<G>(t, h.b2, k, lane);
+        }
+    }
+    if (slot >= 0) {
+        const size_t e = (size_t)b * kSlots + slot;
+        copy_row<G>(out + i * t.dim, t.vals + e * t.dim, t.dim, lane);
+        if (lane == 0) {
+            found[i] = 1;
+            if (scores_out) scores_out[i] = t.scores[e];
+        }
+    } else if (lane == 0) {
+        found[i] = 0;
+    }
+}
+
+hipError_t launch_find_nodigest(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
+                                uint64_t* scores_out, int group, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = blocks_for(n * (uint64_t)group, 256);
+    switch (group) {
+        case 4: k_find_nodigest<4><<<blocks, 256, 0, s>>>(t, n, keys, out, found, scores_out); break;
+        case 16: k_find_nodigest<16><<<blocks, 256, 0, s>>>(t, n, keys, out, found, scores_out); break;
+        default: k_find_nodigest<8><<<blocks, 256, 0, s>>>(t, n, keys, out, found, scores_out); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_find_args(const TableView& t, const FindDescArgs& a, int group, int prefetch_b2, hipStream_t s) {
     if (a.total == 0 || a.nd == 0) return hipSuccess;
     const unsigned blocks = blocks_for(a.total * (uint64_t)group, 256);

@@ -127,6 +127,8 @@ size_t erase_ws_bytes(uint64_t n);
 // launchers (return hipError_t of the last launch)
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_clear_table(const TableView& t, hipStream_t s);
+hipError_t launch_find_nodigest(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
+                                uint64_t* scores_out, int group, hipStream_t s);
 hipError_t launch_find(const TableView& t, uint64_t n, const uint64_t* keys, float* out, uint8_t* found,
                        uint64_t* scores_out, int group, int prefetch_b2, int pairs, hipStream_t s);
 hipError_t launch_find_multi(const TableView& t, const FindDesc* d, uint32_t nd, uint64_t total, int group,
@@ -183,6 +185,7 @@ struct cskv_table {
     int prefetch_b2;    // find loads both candidate digest lines at once
     int blocks_per_cu;  // persistent grid of merged find runs: blocks per compute unit (0 = one group per key)
     int find_pairs;     // find: two keys per lane group
+    int find_digest;    // find: 1 = digest-filtered probes, 0 = the no-digest ablation
     int num_cus;
 };
 

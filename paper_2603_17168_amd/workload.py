@@ -71,6 +71,17 @@ def keys(stream: int, n: int, start: int = 0, device="cpu") -> torch.Tensor:
     return k
 
 
+def keys_at(stream: int, counters: torch.Tensor) -> torch.Tensor:
+    """The keys of stream `stream` at arbitrary counters (< 2**40): keys(stream, n, start) is
+    keys_at(stream, arange(start, start + n))."""
+    ctr = counters.to(torch.int64) | _s64(stream << 40)
+    k = mix64(ctr)
+    bad = (k == 0) | (k == -1)
+    if bool(bad.any()):
+        k = torch.where(bad, mix64(~ctr), k)
+    return k
+
+
 def value_rows(seed: int, vids: torch.Tensor, dim: int) -> torch.Tensor:
     """float32 rows [len(vids), dim]; row r is a pure function of (seed, vids[r])."""
     vids = vids.to(torch.int64)

@@ -200,6 +200,34 @@ def test_api_errors_on_gpu():
     assert lib.cskv_table_bytes(128 * 4, 128, 6) == 0
 
 
+@pytest.mark.parametrize("group", [4, 8, 16])
+def test_find_without_digest_matches(group):
+    """The digest ablation (Exp. 3a) scans every stored key of a candidate bucket; it must give
+    the oracle's results, including after erases that leave stale keys in freed slots and keys
+    re-inserted elsewhere in the same bucket."""
+    say(f"find without digest, group {group}")
+    nb = 8
+    tw = Twin(nb * 128, 8, "dual", "custom", seed=group)
+    tw.gpu.set_tuning(find_group=group, find_digest=0)
+    assert tw.gpu.get_tuning()["find_digest"] == 0
+    rng = np.random.default_rng(group)
+    k = np.array([key_for(3, 3, nb, salt=1 + i) for i in range(100)], dtype=np.uint64)
+    tw.upsert(k, rng.integers(0, 9, k.size).astype(np.uint64))
+    tw.erase(k[:50])
+    tw.find(k)
+    other = np.array([key_for(3, 3, nb, salt=1000 + i) for i in range(60)], dtype=np.uint64)
+    tw.upsert(other, rng.integers(0, 9, other.size).astype(np.uint64))  # takes the freed slots
+    tw.upsert(k[:50], rng.integers(0, 9, 50).astype(np.uint64))  # back in, other slots
+    tw.find(np.concatenate([k, other, np_keys(81, 500)]))
+    for rep in range(4):
+        tw.upsert(np_keys(80, 3000, rep * 1000), rng.integers(0, 20, 3000).astype(np.uint64), evict=True)
+        tw.erase(np_keys(80, 400, rep * 900))
+        tw.find(np_keys(80, 6000))
+    tw.check_table()
+    with pytest.raises(cskv.CskvError):
+        tw.gpu.set_tuning(find_digest=2)
+
+
 def test_launch_shapes_do_not_change_results():
     """Every tuning variant (probe lanes per key, b2 prefetch, route lanes) gives bit-identical
     outputs and tables, and matches the oracle."""
