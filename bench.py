@@ -324,6 +324,57 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
     return out
 
 
+ROLE_MIXES = [("1U", 0, 1, 0), ("2U", 0, 2, 0), ("5U", 0, 5, 0), ("10U", 0, 10, 0),
+              ("4F/5U/1I", 4, 5, 1), ("4F/2U/4I", 4, 2, 4), ("8F/1U/1I", 8, 1, 1)]
+
+
+def bench_roles(dev, log2_cap=26, dim=16, load=0.75, n=1 << 16, calls=200, reps=3):
+    """Concurrency ablation (Exp. 3e): host threads, one stream each, issue `calls` batches of n
+    keys on one 2^26-slot dim-16 LRU table at load 0.75 - finders (100 % hit), updaters
+    (assign of disjoint resident key sets) and inserters (insert_or_assign then erase of their own
+    fresh keys, alternately) - under the triple-group lock and under a reader/writer lock.
+    Rate = all keys of all calls / wall time (best of `reps`)."""
+    cap = 1 << log2_cap
+    t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
+    offered, size = fill(t, load, 1 << 20, dim, 4, 0, dev)
+    resident = gen_keys(4, int(size), 0, device=dev)
+    log(f"roles: prefilled {size} ({size / cap:.3f})")
+    rows = torch.zeros((n, dim), dtype=torch.float32, device=dev)
+    maxf = max(m[1] for m in ROLE_MIXES)
+    maxu = max(m[2] for m in ROLE_MIXES)
+    maxi = max(m[3] for m in ROLE_MIXES)
+    perm = torch.randperm(int(size), device=dev)
+    fkeys = [resident[torch.randint(0, int(size), (n,), device=dev)] for _ in range(maxf)]
+    ukeys = [resident[perm[i * n:(i + 1) * n]] for i in range(maxu)]  # disjoint per updater
+    ikeys = [gen_keys(5, n, i * n, device=dev) for i in range(maxi)]
+    outs = [torch.empty((n, dim), dtype=torch.float32, device=dev) for _ in range(maxf)]
+    flags = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(maxf + maxu + maxi)]
+    res = {}
+    for name, nf, nu, ni in ROLE_MIXES:
+        specs = ([{"op": "find", "calls": calls, "keys": fkeys[i], "values_out": outs[i], "flags": flags[i]}
+                  for i in range(nf)] +
+                 [{"op": "assign", "calls": calls, "keys": ukeys[i], "values": rows, "flags": flags[maxf + i]}
+                  for i in range(nu)] +
+                 [{"op": "insert_erase", "calls": calls, "keys": ikeys[i], "values": rows,
+                   "flags": flags[maxf + maxu + i]} for i in range(ni)])
+        keys_total = len(specs) * calls * n
+        r = {}
+        for mode in ("triple_group", "reader_writer"):
+            t.set_lock_mode(mode)
+            cskv.run_threads(t, specs)  # warm
+            best = min(cskv.run_threads(t, specs) for _ in range(reps))
+            r[mode + "_bkvs"] = round(keys_total / best / 1e6, 3)
+        t.set_lock_mode("none")
+        r["ratio"] = round(r["triple_group_bkvs"] / r["reader_writer_bkvs"], 3)
+        res[name] = r
+        log(f"roles {name}: {r}")
+    final = t.size()
+    del t
+    torch.cuda.empty_cache()
+    return {"workload": f"2^{log2_cap} slots dim {dim} LRU at load {load}; {calls} calls of {n} keys per thread",
+            "final_load": round(final / cap, 4), "mixes": res}
+
+
 def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(0.5, 0.8)):
     """Serving loop: a 2^28-slot dim-128 LRU table (~142 GB) prefilled with ranks 1..2^28;
     requests of lognormal(4096, 1.0) keys clipped to 256..65536, 90 % find / 10 %
@@ -383,6 +434,7 @@ def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
     offered = 0
     tot_keys = 0
     tot_s = 0.0
+    op_s = {"find_hit100": 0.0, "find_hit50": 0.0, "insert_or_assign": 0.0}
     rng = np.random.default_rng(0)
     for lam in loads:
         while o.size() < lam * cap and offered < 2 * cap:
@@ -393,15 +445,30 @@ def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
         q100 = res[rng.integers(0, res.size, batch)]
         q50 = np.concatenate([res[rng.integers(0, res.size, batch // 2)], as_u64(gen_keys(998, batch // 2))])
         fresh = as_u64(gen_keys(997, batch, offered))
+        zeros = np.zeros(batch, np.uint64)
         t0 = time.perf_counter()
         o.find(q100)
+        t1 = time.perf_counter()
         o.find(q50)
-        o.upsert(fresh, np.zeros(batch, np.uint64))
-        tot_s += time.perf_counter() - t0
+        t2 = time.perf_counter()
+        o.upsert(fresh, zeros)
+        t3 = time.perf_counter()
+        op_s["find_hit100"] += t1 - t0
+        op_s["find_hit50"] += t2 - t1
+        op_s["insert_or_assign"] += t3 - t2
+        tot_s += t3 - t0
         tot_keys += 3 * batch
         if lam < 1.0:
             o.erase(fresh)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": tot_keys / tot_s / 1e6, "unit": "M-KV/s", "cores": 1, "kind": "oracle",
+            "per_op_mkvs": {k: round(len(loads) * batch / v / 1e6, 3) for k, v in op_s.items()},
+            "host_cpu": model, "host_logical_cpus": os.cpu_count(),
             "sample": f"sequential C oracle, 2^{sample_log2_cap}-slot dual LRU table filled to loads {loads}; "
                       f"per load one find (100% hit), one find (50% hit) and one insert_or_assign of "
                       f"2^{int(np.log2(batch))} keys; {tot_s:.1f} s timed"}
@@ -465,6 +532,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-roles", action="store_true", help="skip the concurrency ablation (lock modes)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-api", action="store_true", help="skip the contains / find_ptr / assign / find_or_insert rates")
     ap.add_argument("--counter-probe", action="store_true",
@@ -725,6 +793,9 @@ def main():
             top = lv[max(lv)]["continuous_batching"]
             out["latency_ms"]["served_p50"] = top["p50"]
             out["latency_ms"]["served_p99"] = top["p99"]
+    if not args.no_roles:
+        log("concurrency ablation: lock modes")
+        out["roles"] = bench_roles(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the sequential oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(loads)

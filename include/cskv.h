@@ -253,6 +253,37 @@ int cskv_set_tuning(cskv_table* table, int param, int value);
 int cskv_get_tuning(const cskv_table* table, int param);
 
 /*
+ * Concurrent calls from several host threads and streams (Sec. 3.5, the three operation groups
+ * and their compatibility table; Sec. 4.4, the host/device lock).  Roles: readers = find,
+ * contains, find_ptr, size, export, export_if and programs without writes; updaters = assign,
+ * assign_scores; inserters = insert_or_assign, insert_and_evict, find_or_insert, erase, clear,
+ * programs with writes and cskv_serve_trace (one call for the whole trace).
+ *
+ *   CSKV_LOCK_NONE           (default) no ordering across streams: the caller orders its calls
+ *   CSKV_LOCK_TRIPLE_GROUP   readers run together, updaters run together, an inserter runs alone
+ *   CSKV_LOCK_READER_WRITER  readers run together, every updater and inserter runs alone (the
+ *                            conventional lock the paper's Exp. 3e compares against)
+ *
+ * With a lock on, calls are admitted in the order they enter the library (host order across
+ * threads).  A call whose role cannot join the running group starts a new group: its stream is
+ * made to wait (hipStreamWaitEvent) for events recorded after every call of the group before,
+ * so calls of different groups execute in admission order on the GPU while calls of one group
+ * may overlap.  No call waits on the host for GPU work; a thread blocks only while another
+ * thread is still enqueueing a call of the group being closed.  Each call records one event on
+ * its stream.  Concurrent updaters that touch the same key race (last writer unspecified, LFU
+ * increments may be lost); callers give concurrent updaters disjoint keys.  Workspaces must not
+ * be shared by calls that may overlap.  cskv_program_capture takes no role (the replay does).
+ * The lock keeps the latest events of the streams it has seen and may query or wait on them in
+ * later calls; cskv_set_lock_mode (even to the current mode) waits for all of them and forgets
+ * them.  So: call it only while no call is in flight on the table (CSKV_EINVAL otherwise), and
+ * call it after synchronizing, and before destroying, any stream that made calls under a lock.
+ * CSKV_EINVAL for another mode.
+ */
+enum { CSKV_LOCK_NONE = 0, CSKV_LOCK_TRIPLE_GROUP = 1, CSKV_LOCK_READER_WRITER = 2 };
+int cskv_set_lock_mode(cskv_table* table, int mode);
+int cskv_get_lock_mode(const cskv_table* table);
+
+/*
  * LRU logical clock: the number of non-empty upsert calls of an LRU table so far (plus any value
  * set here).  It lives in table storage so that captured programs advance it on every replay.
  * Both calls synchronize the device before reading or writing it.

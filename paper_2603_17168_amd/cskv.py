@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 
 import torch
 
@@ -23,6 +24,8 @@ POLICY = {"custom": 0, "lru": 1, "lfu": 2}
 OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE, OP_ASSIGN, OP_FIND_OR_INSERT = 0, 1, 2, 3, 4, 5
 TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4, "find_pairs": 5, "find_digest": 6}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
+LOCK = {"none": 0, "triple_group": 1, "reader_writer": 2}
+MT_OP = {"find": 0, "assign": 1, "insert_erase": 2}
 
 _lib = None
 
@@ -82,6 +85,9 @@ def lib():
         "cskv_mode": (I, [P]),
         "cskv_policy": (I, [P]),
         "cskv_strerror": (ctypes.c_char_p, [I]),
+        "cskv_set_lock_mode": (I, [P, I]),
+        "cskv_get_lock_mode": (I, [P]),
+        "cskv_mt_run": (I, [P, I, P, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -137,7 +143,7 @@ class Table:
             _check(L.cskv_create(ctypes.byref(h), capacity, bucket_size, dim, MODE[mode], POLICY[policy],
                                  _ptr(self.storage), nbytes, _stream(self.device)), "cskv_create")
         self._h = h
-        self._ws = None
+        self._ws = {}
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -147,10 +153,15 @@ class Table:
 
     # ------------------------------------------------------------------ helpers
     def workspace(self, op: int, n: int) -> torch.Tensor:
+        """Scratch for one call, kept per host thread (calls from different threads may overlap
+        on the GPU under a role lock, so they must not share it)."""
         need = int(lib().cskv_workspace_bytes(self._h, op, n))
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
-        return self._ws
+        tid = threading.get_ident()
+        ws = self._ws.get(tid)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            self._ws[tid] = ws
+        return ws
 
     def _vals(self, v: torch.Tensor, n: int) -> torch.Tensor:
         if v.dtype != torch.float32 or v.device != self.device:
@@ -177,6 +188,16 @@ class Table:
 
     def get_tuning(self) -> dict:
         return {k: int(lib().cskv_get_tuning(self._h, v)) for k, v in TUNE.items()}
+
+    def set_lock_mode(self, mode: str):
+        """"none" (the caller orders calls), "triple_group" or "reader_writer" (calls from several
+        threads / streams are ordered by role; change only while no call is in flight)."""
+        _check(lib().cskv_set_lock_mode(self._h, LOCK[mode]), f"cskv_set_lock_mode({mode})")
+
+    @property
+    def lock_mode(self) -> str:
+        m = int(lib().cskv_get_lock_mode(self._h))
+        return {v: k for k, v in LOCK.items()}[m]
 
     def clear(self):
         with torch.cuda.device(self.device):
@@ -435,3 +456,55 @@ class Program:
     def replay(self, stream=None):
         with torch.cuda.device(self.table.device):
             _check(lib().cskv_program_replay(self._h, self._s(stream)), "cskv_program_replay")
+
+
+class MtThread(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("n", ctypes.c_uint64), ("calls", ctypes.c_uint64),
+                ("d_keys", ctypes.c_void_p), ("d_values", ctypes.c_void_p), ("d_scores", ctypes.c_void_p),
+                ("d_values_out", ctypes.c_void_p), ("d_flags", ctypes.c_void_p), ("d_ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("status", ctypes.c_int), ("hip_error", ctypes.c_int),
+                ("failed_call", ctypes.c_uint64)]
+
+
+def run_threads(table: Table, specs) -> float:
+    """Runs the concurrent-caller driver (include/cskv_mt.h): one host thread and stream per spec,
+    all started together.  A spec is a dict: op ("find" / "assign" / "insert_erase"), calls, keys
+    (int64 [n]), and per op values (float32 [n, dim]), scores (int64 [n] or None), values_out
+    (float32 [n, dim], find) and flags (uint8 [n]).  Workspaces are allocated here, one per
+    thread.  Returns the wall time in ms."""
+    arr = (MtThread * len(specs))()
+    keep = []
+    for i, sp in enumerate(specs):
+        keys = _as_i64(sp["keys"], table.device)
+        n = keys.numel()
+        op = MT_OP[sp["op"]]
+        ws = None
+        if op == MT_OP["assign"]:
+            need = int(lib().cskv_workspace_bytes(table._h, OP_ASSIGN, n))
+        elif op == MT_OP["insert_erase"]:
+            need = max(int(lib().cskv_workspace_bytes(table._h, OP_INSERT_OR_ASSIGN, n)),
+                       int(lib().cskv_workspace_bytes(table._h, OP_ERASE, n)))
+        else:
+            need = 0
+        if need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=table.device)
+        vals = sp.get("values")
+        if vals is not None:
+            vals = table._vals(vals, n)
+        sc = sp.get("scores")
+        if sc is not None:
+            sc = _as_i64(sc, table.device)
+        keep += [keys, ws, vals, sc, sp.get("values_out"), sp["flags"]]
+        arr[i] = MtThread(op, n, int(sp["calls"]), keys.data_ptr(), None if vals is None else vals.data_ptr(),
+                          None if sc is None else sc.data_ptr(),
+                          None if sp.get("values_out") is None else sp["values_out"].data_ptr(),
+                          sp["flags"].data_ptr(), None if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel())
+    torch.cuda.synchronize(table.device)
+    ms = ctypes.c_double(0.0)
+    rc = lib().cskv_mt_run(table._h, len(specs), ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(ms))
+    del keep
+    if rc != 0:
+        bad = [(i, arr[i].status, arr[i].hip_error, arr[i].failed_call) for i in range(len(specs)) if arr[i].status]
+        raise CskvError(f"cskv_mt_run: {lib().cskv_strerror(rc).decode()} ({rc}); "
+                        f"failing threads (index, status, hip error, call): {bad}")
+    return ms.value

@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(256) k_assign(TableView t, UpsertWs w, uint64_
     if (vals) copy_row<G>(t.vals + e * t.dim, vals + i * t.dim, t.dim, lane);
 }
 
-__global__ void k_clock_tick(TableView t) { *t.clock += 1; }
+// an atomic add: updaters may run at the same time on several streams under the role lock
+__global__ void k_clock_tick(TableView t) { atomicAdd(reinterpret_cast<unsigned long long*>(t.clock), 1ull); }
 
 template <int G, bool PTR>
 static void launch_locate_g(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* found, uint64_t* ptrs,

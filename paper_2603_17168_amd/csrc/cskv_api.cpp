@@ -133,12 +133,18 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->blocks_per_cu = 0;
     t->find_pairs = 0;
     t->find_digest = 1;
+    t->roles = new (std::nothrow) TableLock();
+    if (!t->roles) {
+        delete t;
+        return CSKV_ENOMEM;
+    }
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         delete t;
         return CSKV_EHIP;
     }
     t->num_cus = cus;
+    t->device = dev;
     int rc = hip_rc(launch_clear_table(t->view, as_stream(stream)));
     if (rc == CSKV_OK) rc = hip_rc(launch_fill_zero(t->view.clock, 8, as_stream(stream)));
     if (rc != CSKV_OK) {
@@ -156,6 +162,8 @@ int cskv_destroy(cskv_table* table) {
 
 int cskv_clear(cskv_table* table, void* stream) {
     if (!table) return CSKV_EINVAL;
+    RoleScope role(table, kInserter, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_clear_table(table->view, as_stream(stream)));
 }
 
@@ -181,6 +189,8 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
     if (!d_keys || !d_values_out || !d_found) return CSKV_EINVAL;
     if (!aligned(d_keys, 8) || !aligned(d_values_out, 16) || (d_scores_out && !aligned(d_scores_out, 8)))
         return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     if (!table->find_digest)
         return hip_rc(launch_find_nodigest(table->view, n, d_keys, d_values_out, d_found, d_scores_out, table->group,
                                            as_stream(stream)));
@@ -252,6 +262,8 @@ extern "C" {
 int cskv_insert_or_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
                           const uint64_t* d_scores, uint8_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
     UpsertArgs a{n, d_keys, d_values, d_scores, d_status, EvictOut{nullptr, nullptr, nullptr, nullptr}};
+    RoleScope role(table, kInserter, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
@@ -265,16 +277,23 @@ int cskv_insert_and_evict(cskv_table* table, uint64_t n, const uint64_t* d_keys,
     if (!aligned(d_ev_keys, 8) || !aligned(d_ev_values, 16) || !aligned(d_ev_scores, 8) || !aligned(d_n_evicted, 8))
         return CSKV_EINVAL;
     UpsertArgs a{n, d_keys, d_values, d_scores, d_status, EvictOut{d_ev_keys, d_ev_values, d_ev_scores, d_n_evicted}};
+    RoleScope role(table, kInserter, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws, size_t ws_bytes,
                void* stream) {
+    if (!table) return CSKV_EINVAL;
+    RoleScope role(table, kInserter, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return enqueue_erase(table, n, d_keys, d_erased, d_ws, ws_bytes, as_stream(stream));
 }
 
 int cskv_size(cskv_table* table, uint64_t* d_size, void* stream) {
     if (!table || !d_size || !aligned(d_size, 8)) return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_size(table->view, d_size, as_stream(stream)));
 }
 
@@ -285,6 +304,8 @@ int cskv_export(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end, u
     if (!aligned(d_keys, 8) || !aligned(d_count, 8) || (d_values && !aligned(d_values, 16)) ||
         (d_scores && !aligned(d_scores, 8)) || (d_slots && !aligned(d_slots, 8)))
         return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
                                 0, as_stream(stream)));
 }
@@ -297,6 +318,8 @@ int cskv_export_if(cskv_table* table, uint64_t bucket_begin, uint64_t bucket_end
     if (!aligned(d_keys, 8) || !aligned(d_count, 8) || (d_values && !aligned(d_values, 16)) ||
         (d_scores && !aligned(d_scores, 8)) || (d_slots && !aligned(d_slots, 8)))
         return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_export(table->view, bucket_begin, bucket_end, d_keys, d_values, d_scores, d_slots, d_count,
                                 min_score, as_stream(stream)));
 }
@@ -305,6 +328,8 @@ int cskv_contains(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
     if (!d_keys || !d_found || !aligned(d_keys, 8)) return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_locate(table->view, n, d_keys, d_found, nullptr, nullptr, table->group, as_stream(stream)));
 }
 
@@ -315,6 +340,8 @@ int cskv_find_ptr(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint64_
     if (!d_keys || !d_ptrs || !d_found || !aligned(d_keys, 8) || !aligned(d_ptrs, 8) ||
         (d_scores_out && !aligned(d_scores_out, 8)))
         return CSKV_EINVAL;
+    RoleScope role(table, kReader, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return hip_rc(launch_locate(table->view, n, d_keys, d_found, d_ptrs, d_scores_out, table->group, as_stream(stream)));
 }
 
@@ -328,6 +355,8 @@ static int enqueue_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys,
     const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes, false);
     if (rc != CSKV_OK) return rc;
     hipStream_t s = as_stream(stream);
+    RoleScope role(table, kUpdater, s);
+    if (!role.ok()) return CSKV_EHIP;
     const hipError_t e = launch_upsert_prep(table->view, w, n, d_keys, d_scores, a.ev, zero_bytes, s);
     if (e != hipSuccess) return CSKV_EHIP;
     return hip_rc(launch_assign(table->view, w, n, d_keys, d_values, d_scores, d_found, table->group, s));
@@ -350,6 +379,8 @@ int cskv_find_or_insert(cskv_table* table, uint64_t n, const uint64_t* d_keys, c
     if (n && (!d_init_values || !d_values_out)) return CSKV_EINVAL;
     UpsertArgs a{n, d_keys, d_init_values, d_scores, d_status, EvictOut{nullptr, nullptr, nullptr, nullptr}};
     a.out = d_values_out;
+    RoleScope role(table, kInserter, as_stream(stream));
+    if (!role.ok()) return CSKV_EHIP;
     return enqueue_upsert(table, a, d_ws, ws_bytes, as_stream(stream));
 }
 
@@ -396,6 +427,14 @@ int cskv_get_tuning(const cskv_table* table, int param) {
         default: return -1;
     }
 }
+
+int cskv_set_lock_mode(cskv_table* table, int mode) {
+    if (!table || (mode != CSKV_LOCK_NONE && mode != CSKV_LOCK_TRIPLE_GROUP && mode != CSKV_LOCK_READER_WRITER))
+        return CSKV_EINVAL;
+    return table->roles->set_mode(mode) ? CSKV_OK : CSKV_EINVAL;
+}
+
+int cskv_get_lock_mode(const cskv_table* table) { return table ? table->roles->mode() : -1; }
 
 uint64_t cskv_clock(const cskv_table* table) {
     if (!table) return 0;

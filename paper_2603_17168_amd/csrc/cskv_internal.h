@@ -26,6 +26,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "cskv_roles.h"
+
 namespace cskv {
 
 constexpr int kSlots = 128;
@@ -175,6 +177,27 @@ struct UpsertArgs {
 }  // namespace cskv
 
 // the C ABI's opaque table object
+namespace cskv {
+// the role lock's backend: HIP events ordering streams
+struct HipEvents {
+    using Event = hipEvent_t;
+    using Stream = hipStream_t;
+    Event make() {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    }
+    bool record(Event e, Stream s) { return e && hipEventRecord(e, s) == hipSuccess; }
+    bool wait(Stream s, Event e) { return hipStreamWaitEvent(s, e, 0) == hipSuccess; }
+    bool done(Event e) { return hipEventQuery(e) == hipSuccess; }
+    void sync(Event e) { (void)hipEventSynchronize(e); }
+    void destroy(Event e) {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+using TableLock = RoleLock<HipEvents>;
+}  // namespace cskv
+
 struct cskv_table {
     cskv::TableView view;
     uint64_t capacity;
@@ -187,7 +210,34 @@ struct cskv_table {
     int find_pairs;     // find: two keys per lane group
     int find_digest;    // find: 1 = digest-filtered probes, 0 = the no-digest ablation
     int num_cus;
+    int device;  // HIP device the table lives on
+    cskv::TableLock* roles = nullptr;  // role lock across host threads and streams (off in lock mode none)
+    ~cskv_table() { delete roles; }
 };
+
+namespace cskv {
+// holds a table's role for one call when its lock is on: the stream waits for the group before
+// on entry; the call's event is recorded on exit
+class RoleScope {
+  public:
+    RoleScope(cskv_table* t, int role, hipStream_t s) : t_(t), s_(s) {
+        on_ = t && t->roles && t->roles->mode() != kLockNone;
+        if (on_) tk_ = t->roles->acquire(role, s);
+    }
+    ~RoleScope() {
+        if (on_) t_->roles->release(tk_, s_);
+    }
+    bool ok() const { return !on_ || tk_.ok; }
+    RoleScope(const RoleScope&) = delete;
+    RoleScope& operator=(const RoleScope&) = delete;
+
+  private:
+    cskv_table* t_;
+    hipStream_t s_;
+    bool on_ = false;
+    TableLock::Ticket tk_;
+};
+}  // namespace cskv
 
 namespace cskv {
 // validates an upsert and lays out its workspace (CSKV_* code)

@@ -536,11 +536,20 @@ static int build_graph_overlapped(cskv_program* p, hipStream_t s) {
     return hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) == hipSuccess ? CSKV_OK : CSKV_EHIP;
 }
 
+// a program holds its table as one call: an inserter if it changes the table, else a reader
+static int program_role(const cskv_program* p) {
+    for (const Op& o : p->ops)
+        if (o.kind != kFind) return kInserter;
+    return kReader;
+}
+
 extern "C" {
 
 int cskv_program_launch(cskv_program* p, void* stream) {
     if (!p || !p->ready) return CSKV_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RoleScope role(p->table, program_role(p), s);
+    if (!role.ok()) return CSKV_EHIP;
     return p->overlap ? launch_overlapped(p, s) : launch_serial(p, s);
 }
 
@@ -566,7 +575,10 @@ int cskv_program_capture(cskv_program* p, void* stream) {
 
 int cskv_program_replay(cskv_program* p, void* stream) {
     if (!p || !p->ready || !p->exec) return CSKV_EINVAL;
-    return hipGraphLaunch(p->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? CSKV_OK : CSKV_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RoleScope role(p->table, program_role(p), s);
+    if (!role.ok()) return CSKV_EHIP;
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? CSKV_OK : CSKV_EHIP;
 }
 
 }  // extern "C"

@@ -75,6 +75,8 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
     const size_t ups_bytes = align256(upsert_layout(max_n, t->view.nbuckets).total);
     if (ws_bytes < ups_bytes + align256(cfg->arena_budget_bytes)) return CSKV_ENOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    RoleScope role(t, kInserter, s);  // the whole trace holds the table as one inserter
+    if (!role.ok()) return CSKV_EHIP;
     uint8_t* ws = reinterpret_cast<uint8_t*>(d_ws);
     cskv::Ring ring;
     uint8_t* const arena = ws + ups_bytes;
