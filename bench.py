@@ -324,6 +324,60 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
     return out
 
 
+def bench_hybrid(dev, log2_cap=27, dim=64, load=0.5, hbm_value_gib=16, batch=1 << 20, reps=3):
+    """Hybrid HBM + host value storage (Config D, Sec. 3.6 / Exp. 2): a 2^27-slot dim-64 LRU table
+    whose first 16 GiB of value rows are in HBM and the other 16 GiB in pinned host memory,
+    against the same table all in HBM, both at load 0.5: find_ptr and contains (key side only),
+    find (value copy, 100 % hit) and insert_or_assign of fresh keys (erased again).  Median of
+    `reps` event-timed calls of `batch` keys."""
+    cap = 1 << log2_cap
+    hbm_rows = min(cap, (hbm_value_gib << 30) // (dim * 4))
+    res = {}
+    for name, rows_in_hbm in (("hybrid", hbm_rows), ("hbm", None)):
+        t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev, hbm_value_rows=rows_in_hbm)
+        offered, size = fill(t, load, batch, dim, 6, 0, dev)
+        resident = gen_keys(6, int(size), 0, device=dev)
+        q = resident[torch.randint(0, int(size), (batch,), device=dev)]
+        fresh = gen_keys(7, batch, 0, device=dev)
+        rows = torch.zeros((batch, dim), dtype=torch.float32, device=dev)
+        outs = torch.empty((batch, dim), dtype=torch.float32, device=dev)
+        found = torch.empty(batch, dtype=torch.uint8, device=dev)
+        ptrs = torch.empty(batch, dtype=torch.int64, device=dev)
+        status = torch.empty(batch, dtype=torch.uint8, device=dev)
+        erased = torch.empty(batch, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+
+        def timed(fn, after=None):
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+                if after:
+                    after()
+            return round(batch / float(np.median(ms)) / 1e6, 3)
+
+        r = {"find_ptr_bkvs": timed(lambda: t.find_ptr(q, ptrs_out=ptrs, found_out=found)),
+             "contains_bkvs": timed(lambda: t.contains(q, found_out=found)),
+             "find_bkvs": timed(lambda: t.find(q, values_out=outs, found_out=found, want_scores=False)),
+             "insert_or_assign_bkvs": timed(lambda: t.insert_or_assign(fresh, rows, status_out=status),
+                                            after=lambda: (t.erase(fresh, erased_out=erased),
+                                                           torch.cuda.synchronize())),
+             "load": round(size / cap, 4), "hbm_value_rows": t.hbm_value_rows}
+        res[name] = r
+        log(f"hybrid {name}: {r}")
+        del t, resident, q, fresh, rows, outs
+        torch.cuda.empty_cache()
+    for k in ("find_ptr_bkvs", "contains_bkvs", "find_bkvs", "insert_or_assign_bkvs"):
+        res.setdefault("hybrid_vs_hbm", {})[k] = round(res["hybrid"][k] / res["hbm"][k], 4)
+    res["workload"] = (f"2^{log2_cap} slots dim {dim} dual LRU at load {load}; {hbm_value_gib} GiB of value rows "
+                       f"in HBM, the rest in pinned host memory; {batch}-key calls")
+    return res
+
+
 ROLE_MIXES = [("1U", 0, 1, 0), ("2U", 0, 2, 0), ("5U", 0, 5, 0), ("10U", 0, 10, 0),
               ("4F/5U/1I", 4, 5, 1), ("4F/2U/4I", 4, 2, 4), ("8F/1U/1I", 8, 1, 1)]
 
@@ -533,6 +587,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-roles", action="store_true", help="skip the concurrency ablation (lock modes)")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid HBM + host value storage rates")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-api", action="store_true", help="skip the contains / find_ptr / assign / find_or_insert rates")
     ap.add_argument("--counter-probe", action="store_true",
@@ -793,6 +848,9 @@ def main():
             top = lv[max(lv)]["continuous_batching"]
             out["latency_ms"]["served_p50"] = top["p50"]
             out["latency_ms"]["served_p99"] = top["p99"]
+    if not args.no_hybrid:
+        log("hybrid HBM + host value storage")
+        out["hybrid"] = bench_hybrid(dev)
     if not args.no_roles:
         log("concurrency ablation: lock modes")
         out["roles"] = bench_roles(dev)

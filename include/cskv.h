@@ -104,6 +104,34 @@ size_t cskv_table_bytes(uint64_t capacity, uint32_t bucket_size, uint32_t dim);
 int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
                 int score_policy, void* d_storage, size_t storage_bytes, void* stream);
 
+/*
+ * Tiered value storage (Sec. 3.6 key-value separation, Sec. 4.2 HBM watermark): digests, keys,
+ * scores and the first hbm_value_rows value rows live in HBM; the remaining
+ * capacity - hbm_value_rows rows live in pinned host memory that kernels read and write through
+ * its device alias (no CPU thread on the data path).  A value row's address follows from its
+ * position: slot e = bucket * 128 + slot holds its row in HBM at e * dim * 4 if e <
+ * hbm_value_rows, else in host memory at (e - hbm_value_rows) * dim * 4.
+ *   cskv_table_bytes_tiered: device bytes for the table with hbm_value_rows rows in HBM
+ *                            (0 on bad arguments or hbm_value_rows > capacity);
+ *   cskv_host_value_bytes:   host bytes for the rest;
+ *   cskv_create_tiered:      cskv_create with h_values = host memory from hipHostMalloc (or any
+ *                            pinned allocation hipHostGetDevicePointer accepts), 16-byte aligned,
+ *                            host_bytes >= cskv_host_value_bytes; h_values is ignored when
+ *                            hbm_value_rows == capacity.  The host memory stays the caller's and
+ *                            must outlive the table.  CSKV_EINVAL if it is not pinned.
+ * Every call works unchanged on a tiered table; find_ptr and cskv_row_address may return
+ * device aliases of host memory.  cskv_create is cskv_create_tiered with hbm_value_rows =
+ * capacity.
+ */
+size_t cskv_table_bytes_tiered(uint64_t capacity, uint32_t bucket_size, uint32_t dim, uint64_t hbm_value_rows);
+size_t cskv_host_value_bytes(uint64_t capacity, uint32_t dim, uint64_t hbm_value_rows);
+int cskv_create_tiered(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
+                       int score_policy, void* d_storage, size_t storage_bytes, uint64_t hbm_value_rows,
+                       void* h_values, size_t host_bytes, void* stream);
+uint64_t cskv_hbm_value_rows(const cskv_table* table);
+/* device address of the value row of slot e (= bucket * 128 + slot); 0 if e >= capacity */
+uint64_t cskv_row_address(const cskv_table* table, uint64_t slot);
+
 /* Frees the host object (never the storage).  NULL is accepted. */
 int cskv_destroy(cskv_table* table);
 

@@ -86,6 +86,11 @@ def lib():
         "cskv_policy": (I, [P]),
         "cskv_strerror": (ctypes.c_char_p, [I]),
         "cskv_set_lock_mode": (I, [P, I]),
+        "cskv_table_bytes_tiered": (SZ, [U64, U32, U32, U64]),
+        "cskv_host_value_bytes": (SZ, [U64, U32, U64]),
+        "cskv_create_tiered": (I, [ctypes.POINTER(P), U64, U32, U32, I, I, P, SZ, U64, P, SZ, P]),
+        "cskv_hbm_value_rows": (U64, [P]),
+        "cskv_row_address": (U64, [P, U64]),
         "cskv_get_lock_mode": (I, [P]),
         "cskv_mt_run": (I, [P, I, P, ctypes.POINTER(ctypes.c_double)]),
     }
@@ -121,27 +126,38 @@ def _as_i64(t: torch.Tensor, device) -> torch.Tensor:
 
 
 class Table:
-    """A cache-semantic hash table in device memory (one caller-visible storage tensor)."""
+    """A cache-semantic hash table in device memory (one caller-visible storage tensor).
+
+    hbm_value_rows (default: all) keeps only that many value rows in HBM; the rest live in a
+    pinned host tensor (``host_values``) that the kernels reach through its device alias."""
 
     def __init__(self, capacity: int, dim: int, mode: str = "dual", policy: str = "lru",
-                 device="cuda", bucket_size: int = 128):
+                 device="cuda", bucket_size: int = 128, hbm_value_rows: int | None = None):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the table lives in GPU memory")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         L = lib()
-        nbytes = int(L.cskv_table_bytes(capacity, bucket_size, dim))
+        hbm_rows = int(capacity if hbm_value_rows is None else hbm_value_rows)
+        nbytes = int(L.cskv_table_bytes_tiered(capacity, bucket_size, dim, hbm_rows))
         if nbytes == 0:
-            raise CskvError(f"invalid table geometry capacity={capacity} bucket_size={bucket_size} dim={dim}")
+            raise CskvError(f"invalid table geometry capacity={capacity} bucket_size={bucket_size} dim={dim} "
+                            f"hbm_value_rows={hbm_rows}")
+        self.hbm_value_rows = hbm_rows
+        self.host_values = None
+        host_bytes = int(L.cskv_host_value_bytes(capacity, dim, hbm_rows))
+        if host_bytes:
+            self.host_values = torch.empty(host_bytes, dtype=torch.uint8, pin_memory=True)
         self.capacity, self.dim, self.bucket_size = int(capacity), int(dim), int(bucket_size)
         self.mode, self.policy = mode, policy
         self.n_buckets = self.capacity // self.bucket_size
         self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(L.cskv_create(ctypes.byref(h), capacity, bucket_size, dim, MODE[mode], POLICY[policy],
-                                 _ptr(self.storage), nbytes, _stream(self.device)), "cskv_create")
+            _check(L.cskv_create_tiered(ctypes.byref(h), capacity, bucket_size, dim, MODE[mode], POLICY[policy],
+                                        _ptr(self.storage), nbytes, hbm_rows, _ptr(self.host_values), host_bytes,
+                                        _stream(self.device)), "cskv_create_tiered")
         self._h = h
         self._ws = {}
 
@@ -188,6 +204,11 @@ class Table:
 
     def get_tuning(self) -> dict:
         return {k: int(lib().cskv_get_tuning(self._h, v)) for k, v in TUNE.items()}
+
+    def row_address(self, slot: int) -> int:
+        """Device address of the value row of slot e = bucket * 128 + slot (a device alias of host
+        memory for rows past hbm_value_rows)."""
+        return int(lib().cskv_row_address(self._h, int(slot)))
 
     def set_lock_mode(self, mode: str):
         """"none" (the caller orders calls), "triple_group" or "reader_writer" (calls from several

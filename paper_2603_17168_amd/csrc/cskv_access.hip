@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_locate(TableView t, uint64_t n, const u
         return;
     }
     const size_t e = (size_t)b * kSlots + slot;
-    if (PTR) ptrs[i] = (uint64_t)(uintptr_t)(t.vals + e * t.dim);
+    if (PTR) ptrs[i] = (uint64_t)(uintptr_t)t.row(e);
     if (scores) scores[i] = t.scores[e];
 }
 
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_assign(TableView t, UpsertWs w, uint64_
         t.scores[e] = ns;
         t.bmin[2 * (size_t)b + 1] = 0;
     }
-    if (vals) copy_row<G>(t.vals + e * t.dim, vals + i * t.dim, t.dim, lane);
+    if (vals) copy_row<G>(t.row(e), vals + i * t.dim, t.dim, lane);
 }
 
 // an atomic add: updaters may run at the same time on several streams under the role lock

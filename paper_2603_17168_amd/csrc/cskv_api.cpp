@@ -11,13 +11,13 @@ namespace cskv {
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-StorageLayout storage_layout(uint64_t nb, uint32_t dim) {
+StorageLayout storage_layout(uint64_t nb, uint32_t dim, uint64_t hbm_rows) {
     StorageLayout L;
     size_t o = 0;
     L.off_dig = o;    o = align256(o + nb * kSlots);
     L.off_keys = o;   o = align256(o + nb * kSlots * 8);
     L.off_scores = o; o = align256(o + nb * kSlots * 8);
-    L.off_vals = o;   o = align256(o + nb * kSlots * (size_t)dim * 4);
+    L.off_vals = o;   o = align256(o + hbm_rows * (size_t)dim * 4);
     L.off_cnt = o;    o = align256(o + nb * 4);
     L.off_bmin = o;   o = align256(o + nb * 16);
     L.off_clock = o;  o = align256(o + 8);
@@ -93,11 +93,30 @@ extern "C" {
 size_t cskv_table_bytes(uint64_t capacity, uint32_t bucket_size, uint32_t dim) {
     uint64_t nb;
     if (!valid_geometry(capacity, bucket_size, dim, &nb)) return 0;
-    return storage_layout(nb, dim).total;
+    return storage_layout(nb, dim, capacity).total;
+}
+
+size_t cskv_table_bytes_tiered(uint64_t capacity, uint32_t bucket_size, uint32_t dim, uint64_t hbm_value_rows) {
+    uint64_t nb;
+    if (!valid_geometry(capacity, bucket_size, dim, &nb) || hbm_value_rows > capacity) return 0;
+    return storage_layout(nb, dim, hbm_value_rows).total;
+}
+
+size_t cskv_host_value_bytes(uint64_t capacity, uint32_t dim, uint64_t hbm_value_rows) {
+    uint64_t nb;
+    if (!valid_geometry(capacity, (uint32_t)kSlots, dim, &nb) || hbm_value_rows > capacity) return 0;
+    return (size_t)(capacity - hbm_value_rows) * dim * 4;
 }
 
 int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
                 int score_policy, void* d_storage, size_t storage_bytes, void* stream) {
+    return cskv_create_tiered(out, capacity, bucket_size, dim, mode, score_policy, d_storage, storage_bytes,
+                              capacity, nullptr, 0, stream);
+}
+
+int cskv_create_tiered(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint32_t dim, int mode,
+                       int score_policy, void* d_storage, size_t storage_bytes, uint64_t hbm_value_rows,
+                       void* h_values, size_t host_bytes, void* stream) {
     if (!out || !d_storage) return CSKV_EINVAL;
     *out = nullptr;
     if (mode != CSKV_MODE_SINGLE && mode != CSKV_MODE_DUAL) return CSKV_EINVAL;
@@ -106,9 +125,21 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     if (bucket_size != (uint32_t)kSlots) return CSKV_EUNSUPPORTED;
     uint64_t nb;
     if (!valid_geometry(capacity, bucket_size, dim, &nb)) return CSKV_EINVAL;
-    if (!aligned(d_storage, 256)) return CSKV_EINVAL;
-    const StorageLayout L = storage_layout(nb, dim);
+    if (!aligned(d_storage, 256) || hbm_value_rows > capacity) return CSKV_EINVAL;
+    const StorageLayout L = storage_layout(nb, dim, hbm_value_rows);
     if (storage_bytes < L.total) return CSKV_ENOMEM;
+    // the host tier: pinned host memory, addressed by kernels through its device alias
+    float* host_rows = nullptr;
+    if (hbm_value_rows < capacity) {
+        if (!h_values || !aligned(h_values, 16)) return CSKV_EINVAL;
+        if (host_bytes < (size_t)(capacity - hbm_value_rows) * dim * 4) return CSKV_ENOMEM;
+        void* dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, h_values, 0) != hipSuccess || !dptr) {
+            (void)hipGetLastError();
+            return CSKV_EINVAL;  // not pinned (hipHostMalloc) host memory
+        }
+        host_rows = reinterpret_cast<float*>(dptr);
+    }
     cskv_table* t = new (std::nothrow) cskv_table;
     if (!t) return CSKV_ENOMEM;
     uint8_t* base = reinterpret_cast<uint8_t*>(d_storage);
@@ -116,6 +147,8 @@ int cskv_create(cskv_table** out, uint64_t capacity, uint32_t bucket_size, uint3
     t->view.keys = reinterpret_cast<uint64_t*>(base + L.off_keys);
     t->view.scores = reinterpret_cast<uint64_t*>(base + L.off_scores);
     t->view.vals = reinterpret_cast<float*>(base + L.off_vals);
+    t->view.vals_host = host_rows;
+    t->view.hbm_rows = hbm_value_rows;
     t->view.cnt = reinterpret_cast<uint32_t*>(base + L.off_cnt);
     t->view.bmin = reinterpret_cast<uint64_t*>(base + L.off_bmin);
     t->view.clock = reinterpret_cast<uint64_t*>(base + L.off_clock);
@@ -451,6 +484,12 @@ int cskv_set_clock(cskv_table* table, uint64_t clock) {
 }
 
 uint64_t cskv_num_buckets(const cskv_table* table) { return table ? table->view.nbuckets : 0; }
+uint64_t cskv_hbm_value_rows(const cskv_table* table) { return table ? table->view.hbm_rows : 0; }
+
+uint64_t cskv_row_address(const cskv_table* table, uint64_t slot) {
+    if (!table || slot >= table->capacity) return 0;
+    return (uint64_t)(uintptr_t)table->view.row(slot);
+}
 uint32_t cskv_dim(const cskv_table* table) { return table ? table->view.dim : 0; }
 int cskv_mode(const cskv_table* table) { return table ? table->mode : -1; }
 int cskv_policy(const cskv_table* table) { return table ? table->policy : -1; }

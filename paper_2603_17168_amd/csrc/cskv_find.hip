@@ -36,7 +36,7 @@ __device__ __forceinline__ void find_one(const TableView& t, uint64_t k, float* 
     }
     if (slot >= 0) {
         const size_t e = (size_t)b * kSlots + slot;
-        copy_row<G>(out_row, t.vals + e * t.dim, t.dim, lane);
+        copy_row<G>(out_row, t.row(e), t.dim, lane);
         if (lane == 0) {
             *found = 1;
             if (score_out) *score_out = t.scores[e];
@@ -118,8 +118,8 @@ __device__ __forceinline__ void find_pair(const TableView& t, uint64_t kA, uint6
     }
     // rows: both reads issued before the writes
     const uint32_t chunks = t.dim >> 2;
-    const uint4* srcA = reinterpret_cast<const uint4*>(t.vals + ((size_t)bkA * kSlots + (slA < 0 ? 0 : slA)) * t.dim);
-    const uint4* srcB = reinterpret_cast<const uint4*>(t.vals + ((size_t)bkB * kSlots + (slB < 0 ? 0 : slB)) * t.dim);
+    const uint4* srcA = reinterpret_cast<const uint4*>(t.row((size_t)bkA * kSlots + (slA < 0 ? 0 : slA)));
+    const uint4* srcB = reinterpret_cast<const uint4*>(t.row((size_t)bkB * kSlots + (slB < 0 ? 0 : slB)));
     uint4* dA = reinterpret_cast<uint4*>(outA);
     uint4* dB = reinterpret_cast<uint4*>(outB);
     for (uint32_t c = lane; c < chunks; c += G) {
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_find_nodigest(TableView t, uint64_t n, 
     }
     if (slot >= 0) {
         const size_t e = (size_t)b * kSlots + slot;
-        copy_row<G>(out + i * t.dim, t.vals + e * t.dim, t.dim, lane);
+        copy_row<G>(out + i * t.dim, t.row(e), t.dim, lane);
         if (lane == 0) {
             found[i] = 1;
             if (scores_out) scores_out[i] = t.scores[e];

@@ -41,15 +41,22 @@ struct TableView {
     uint8_t* dig;
     uint64_t* keys;
     uint64_t* scores;
-    float* vals;
+    float* vals;       // value rows [0, hbm_rows), in HBM
+    float* vals_host;  // value rows [hbm_rows, nbuckets * 128), pinned host memory (device address)
     uint32_t* cnt;
     uint64_t* bmin;
     uint64_t* clock;
     uint64_t nbuckets;
+    uint64_t hbm_rows;  // nbuckets * 128 unless the table has a host value tier
     uint32_t bmask;  // nbuckets - 1
     uint32_t dim;
     int dual;
     int policy;
+
+    // the value row of slot e (= bucket * 128 + slot): position-based, no per-entry pointer
+    __host__ __device__ __forceinline__ float* row(size_t e) const {
+        return e < hbm_rows ? vals + e * dim : vals_host + (e - hbm_rows) * dim;
+    }
 };
 
 struct DedupeEntry {
@@ -122,7 +129,7 @@ struct UpsertLayout {
     int list_mode;
 };
 
-StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim);
+StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim, uint64_t hbm_rows);
 UpsertLayout upsert_layout(uint64_t n, uint64_t nbuckets);
 size_t erase_ws_bytes(uint64_t n);
 

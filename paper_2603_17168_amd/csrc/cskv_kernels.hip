@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(64) k_export(TableView t, uint64_t b0, uint64_
             for (uint32_t x = lane; x < (uint32_t)c * chunks; x += 64) {
                 const uint32_t j = x / chunks, cc = x - j * chunks;
                 reinterpret_cast<uint4*>(vals + (base + j) * t.dim)[cc] =
-                    reinterpret_cast<const uint4*>(t.vals + (eb + sl[j]) * t.dim)[cc];
+                    reinterpret_cast<const uint4*>(t.row(eb + sl[j]))[cc];
             }
         }
         __syncthreads();

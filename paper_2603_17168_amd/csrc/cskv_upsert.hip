@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
         const int x = __ffs(ub) - 1;
         const int us = __shfl((int)e.slot, x, GA);
         const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
-        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
+        uint4* dst = reinterpret_cast<uint4*>(t.row(eb + us));
         if (w.out) {
             uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
             for (uint32_t c = lane; c < chunks; c += GA) o[c] = dst[c];
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
         const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
         const bool xe = __shfl((int)evicts, x, GA) != 0;
         const int xi = __shfl(evi, x, GA);
-        uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + ns) * t.dim);
+        uint4* dst = reinterpret_cast<uint4*>(t.row(eb + ns));
         const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
         if (xe && ev.vals) {
             uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                 const int x = __ffsll((unsigned long long)ub) - 1;
                 const int us = __shfl((int)e.slot, x);
                 const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x);
-                uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + us) * t.dim);
+                uint4* dst = reinterpret_cast<uint4*>(t.row(eb + us));
                 if (w.out) {  // find_or_insert: the resident row stays and is returned
                     uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
                     for (uint32_t c = lane; c < chunks; c += 64) o[c] = dst[c];
@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         }
         // rows of admitted inserts: chunk c by lane c mod 64; victims copied out first
         for (int j = 0; j < nadm; ++j) {
-            uint4* dst = reinterpret_cast<uint4*>(t.vals + (eb + dslot[j]) * t.dim);
+            uint4* dst = reinterpret_cast<uint4*>(t.row(eb + dslot[j]));
             const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)(uint32_t)cw[j] * t.dim);
             if (j >= nfree && ev.vals) {
                 uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + (uint64_t)(j - nfree)) * t.dim);

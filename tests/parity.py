@@ -24,8 +24,8 @@ def bits(t: torch.Tensor) -> torch.Tensor:
 
 class Twin:
     def __init__(self, capacity: int, dim: int, mode: str = "dual", policy: str = "custom", seed: int = 1,
-                 device="cuda"):
-        self.gpu = cskv.Table(capacity, dim, mode=mode, policy=policy, device=device)
+                 device="cuda", hbm_value_rows=None):
+        self.gpu = cskv.Table(capacity, dim, mode=mode, policy=policy, device=device, hbm_value_rows=hbm_value_rows)
         self.ora = oracle.Oracle(capacity // 128, 128, MODE[mode], POLICY[policy])
         self.dim = dim
         self.seed = seed
@@ -134,14 +134,25 @@ class Twin:
             return of
         gk, gv, gs, gsl = self.gpu.export()
         slot_of = dict(zip(as_u64(gk).tolist(), as_u64(gsl).tolist()))
-        row_of = {int(sl): i for i, sl in enumerate(as_u64(gsl).tolist())}
         rb = self.dim * 4
-        i0 = hit[0]
-        base = int(gp[i0]) - slot_of[int(keys[i0])] * rb
+        hbm = self.gpu.hbm_value_rows
+        hbm_base = self.gpu.row_address(0) if hbm > 0 else None
+        host_base = self.gpu.row_address(hbm) if hbm < self.gpu.capacity else None
+        store = self.gpu.storage.cpu()
+        host = None if self.gpu.host_values is None else self.gpu.host_values.view(torch.int32)
+        _, ov, _ = self.ora.find(keys)
         for i in hit:
             sl = slot_of[int(keys[i])]
-            assert int(gp[i]) == base + sl * rb, "pointer does not address the key's slot"
+            # position-based addressing: one linear map per storage region
+            want = hbm_base + sl * rb if sl < hbm else host_base + (sl - hbm) * rb
+            assert int(gp[i]) == want, "pointer does not address the key's slot"
             assert sl // 128 == int(ob[i]), "pointer outside the key's bucket"
+            if sl < hbm:  # the row at the pointer is the key's row
+                off = int(gp[i]) - self.gpu.storage.data_ptr()
+                got = store[off:off + rb].view(torch.int32)
+            else:
+                got = host[(sl - hbm) * self.dim:(sl - hbm + 1) * self.dim]
+            assert torch.equal(got, bits(self.rows(ov[i:i + 1]))[0]), "the row at the pointer differs"
         assert np.array_equal(as_u64(sc.cpu())[hit], osc[hit]), "find_ptr scores differ"
         return of
 

@@ -12,8 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    with open(os.path.join(ROOT, "include", "cskv.h")) as f:
-        text = f.read()
+    text = ""
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            with open(os.path.join(ROOT, "include", name)) as f:
+                text += f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(cskv_[a-z_]+)\s*\(", text)))
 
@@ -22,6 +25,7 @@ def test_library_exports_every_declared_function():
     lib = cskv.lib()
     names = declared_functions()
     assert len(names) >= 15
+    assert "cskv_mt_run" in names and "cskv_create_tiered" in names
     for n in names:
         assert hasattr(lib, n), n
 
@@ -66,3 +70,25 @@ def test_null_table_calls():
     assert lib.cskv_clock(None) == 0
     assert lib.cskv_destroy(None) == 0
     assert lib.cskv_strerror(-2) == b"storage or workspace too small"
+
+
+def test_tiered_bytes():
+    """Value rows past hbm_value_rows move from device storage to host memory (Sec. 3.6)."""
+    lib = cskv.lib()
+    cap, dim = 128 * 64, 16
+    full = lib.cskv_table_bytes(cap, 128, dim)
+    assert lib.cskv_table_bytes_tiered(cap, 128, dim, cap) == full
+    assert lib.cskv_host_value_bytes(cap, dim, cap) == 0
+    for h in (0, 1000, cap // 2):
+        dev = lib.cskv_table_bytes_tiered(cap, 128, dim, h)
+        assert abs((full - dev) - (cap - h) * dim * 4) <= 256
+        assert lib.cskv_host_value_bytes(cap, dim, h) == (cap - h) * dim * 4
+    assert lib.cskv_table_bytes_tiered(cap, 128, dim, cap + 1) == 0
+    assert lib.cskv_host_value_bytes(cap, dim, cap + 1) == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    # a host tier without host memory, or with too little, fails before any device work
+    assert lib.cskv_create_tiered(ctypes.byref(h), cap, 128, dim, 2, 0, fake, 1 << 40, 1000, None, 0, None) == -1
+    assert lib.cskv_create_tiered(ctypes.byref(h), cap, 128, dim, 2, 0, fake, 1 << 40, cap + 1, None, 0, None) == -1
+    assert lib.cskv_create_tiered(ctypes.byref(h), cap, 128, dim, 2, 0, fake, 1 << 40, 1000, fake, 16, None) == -2
+    assert lib.cskv_row_address(None, 0) == 0

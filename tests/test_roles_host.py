@@ -8,7 +8,7 @@ import subprocess
 
 import pytest
 
-SRC = pathlib.Path(__file__).parent / "native" / "roles_host_test.cpp"
+SRC = pathlib.Path(__file__).parent / "cpp" / "roles_host_test.cpp"
 
 
 @pytest.fixture(scope="module")
