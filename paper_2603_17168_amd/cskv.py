@@ -159,7 +159,7 @@ class Table:
                                         _ptr(self.storage), nbytes, hbm_rows, _ptr(self.host_values), host_bytes,
                                         _stream(self.device)), "cskv_create_tiered")
         self._h = h
-        self._ws = {}
+        self._ws = threading.local()
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -172,11 +172,10 @@ class Table:
         """Scratch for one call, kept per host thread (calls from different threads may overlap
         on the GPU under a role lock, so they must not share it)."""
         need = int(lib().cskv_workspace_bytes(self._h, op, n))
-        tid = threading.get_ident()
-        ws = self._ws.get(tid)
+        ws = getattr(self._ws, "t", None)
         if ws is None or ws.numel() < need:
             ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
-            self._ws[tid] = ws
+            self._ws.t = ws
         return ws
 
     def _vals(self, v: torch.Tensor, n: int) -> torch.Tensor:
