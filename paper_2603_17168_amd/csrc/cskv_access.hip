@@ -70,14 +70,17 @@ __global__ void __launch_bounds__(256) k_assign(TableView t, UpsertWs w, uint64_
     if (found && lane == 0) found[i] = slot >= 0;
     if (slot < 0) return;
     const uint32_t p = w.slot_of[i];
-    const DedupeEntry de = w.dd[p];
-    if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    const bool dups = w.ctr[kCtrDup] != 0;  // else every occurrence is its key's only one
+    if (dups) {
+        const DedupeEntry de = w.dd[p];
+        if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    }
     const size_t e = (size_t)b * kSlots + slot;
     if (lane == 0) {
         uint64_t ns;
         if (t.policy == 0) ns = scores[i];
         else if (t.policy == 1) ns = *t.clock + 1;  // advanced by k_clock_tick after this kernel
-        else ns = sat_add(t.scores[e], w.sat[p] ? ~0ull : w.inc[p]);
+        else ns = sat_add(t.scores[e], dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull));
         t.scores[e] = ns;
         t.bmin[2 * (size_t)b + 1] = 0;
     }

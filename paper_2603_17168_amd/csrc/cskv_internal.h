@@ -35,7 +35,7 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint8_t kInsertSlot = 0xFF;
 constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
-enum Counter { kCtrSlow = 0, kCtrTouched = 1 };
+enum Counter { kCtrSlow = 0, kCtrTouched = 1, kCtrDup = 2 };  // kCtrDup: the call repeats a key
 
 struct TableView {
     uint8_t* dig;

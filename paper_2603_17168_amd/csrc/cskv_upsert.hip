@@ -90,6 +90,7 @@ __global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_
         }
         if (old == k) {
             atomicMax(&w.dd[p].last, (uint32_t)(i + 1));
+            w.ctr[kCtrDup] = 1;  // later passes read the set only when some key repeats
             break;
         }
         p = (p + 1) & mask;
@@ -111,8 +112,11 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     const int lane = glane<G>();
     const uint32_t p = w.slot_of[i];
     if (p == kNoSlot) return;
-    const DedupeEntry de = w.dd[p];
-    if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    const bool dups = w.ctr[kCtrDup] != 0;  // else every occurrence is its key's last and only one
+    if (dups) {
+        const DedupeEntry de = w.dd[p];
+        if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    }
     const uint64_t k = keys[i];
     const uint64_t clock = *t.clock + 1;  // LRU: this call's clock (advanced after routing)
     const KeyHash h = hash_key(t, k);
@@ -127,7 +131,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         tgt = h.b2;
     }
     uint64_t inc = 0;
-    if (t.policy == 2) inc = w.sat[p] ? ~0ull : w.inc[p];
+    if (t.policy == 2) inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);
     uint64_t ns;
     uint8_t islot;
     if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
@@ -687,7 +691,7 @@ __global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t*
     if (i >= n) return;
     const uint32_t p = w.slot_of[i];
     if (status) status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
-    if (w.out && p != kNoSlot) {  // find_or_insert: a repeated key returns its last occurrence's row
+    if (w.out && p != kNoSlot && w.ctr[kCtrDup]) {  // find_or_insert: a repeated key returns its last occurrence's row
         const DedupeEntry de = w.dd[p];
         const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
         if (last != (uint32_t)i) {
