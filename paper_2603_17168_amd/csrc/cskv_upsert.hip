@@ -296,31 +296,20 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
                 if (!(taken >> q & 1u)) lm = sc[q] < lm ? sc[q] : lm;
             const uint64_t gm = gmin_u64<GA>(lm);
             if (!(s_in > gm)) break;  // rejected, and so is every later insert
-            uint32_t tie = 0;  // this lane's unclaimed slots at the minimum score
-#pragma unroll
-            for (int q = 0; q < SPL; ++q)
-                if (!(taken >> q & 1u) && sc[q] == gm) tie |= 1u << q;
             uint64_t lk = ~0ull;
             int lslot = -1;
-            uint64_t gk = 0;
-            if (gsum_i<GA>(__popc(tie)) == 1 && !ev.keys) {
-                // a unique minimum: it is the victim, and its key is needed by nobody
-                if (tie) lslot = lane * SPL + __ffs(tie) - 1;
-            } else {
 #pragma unroll
-                for (int q = 0; q < SPL; ++q) {
-                    if (tie >> q & 1u) {  // keys only for slots tied at the minimum
-                        const uint64_t kq = t.keys[eb + lane * SPL + q];
-                        if (kq < lk) {
-                            lk = kq;
-                            lslot = lane * SPL + q;
-                        }
+            for (int q = 0; q < SPL; ++q) {
+                if (!(taken >> q & 1u) && sc[q] == gm) {  // keys only for slots tied at the minimum
+                    const uint64_t kq = t.keys[eb + lane * SPL + q];
+                    if (kq < lk) {
+                        lk = kq;
+                        lslot = lane * SPL + q;
                     }
                 }
-                gk = gmin_u64<GA>(lk);
-                if (lk != gk) lslot = -1;
             }
-            const uint32_t ob = (uint32_t)((__ballot(lslot >= 0) >> gshift) & 0xFFFFu);
+            const uint64_t gk = gmin_u64<GA>(lk);
+            const uint32_t ob = (uint32_t)((__ballot(lslot >= 0 && lk == gk) >> gshift) & 0xFFFFu);
             const int ol = __ffs(ob) - 1;
             const int vsl = __shfl(lslot, ol, GA);
             if (lane == ol) taken |= 1u << (vsl & 7);
