@@ -64,6 +64,8 @@ def _load():
     lib.ora_export_if.restype = U64
     lib.ora_export_if.argtypes = [P, U64, U64, U64, P, P, P, P]
     lib.ora_stats.argtypes = [P, P]
+    lib.ora_set_subrounds.restype = ctypes.c_int
+    lib.ora_set_subrounds.argtypes = [P, ctypes.c_uint32]
     lib.ora_reset_stats.argtypes = [P]
     _lib = lib
     return lib
@@ -195,6 +197,11 @@ class Oracle:
         b = np.zeros(cap, dtype=np.uint64)
         c = int(self.lib.ora_export_if(self.h, b0, b1, int(min_score), _p(k), _p(v), _p(s), _p(b)))
         return k[:c], v[:c], s[:c], b[:c]
+
+    def set_subrounds(self, r: int):
+        """Route sub-rounds per upsert call (1..64; 1 = the whole batch routes at once)."""
+        if self.lib.ora_set_subrounds(self.h, int(r)) != 0:
+            raise ValueError("subrounds must be 1..64")
 
     def stats(self):
         out = np.zeros(9, dtype=np.uint64)

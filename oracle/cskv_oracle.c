@@ -40,6 +40,11 @@
  *        bucket the minimum entry by (score, key) is evicted when the new score is
  *        strictly greater than its score (admission control, Sec. 3.3), else the key is
  *        rejected.  Evicted entries are reported with the score and value they had.
+ *     Sub-rounds (a semantic setting, 1 by default; the paper's batches are r = 1): with r
+ *        sub-rounds the call's N distinct operations, ordered by the index of their key's
+ *        last occurrence, are cut into r chunks - operation of rank q goes to chunk
+ *        floor(q * r / N) - and steps 3 and 4 run chunk after chunk, each routing against
+ *        the table the chunks before it left.  Steps 1, 2 and the statuses are per call.
  *
  *   erase: every present key is removed; erased[i] tells whether key[i] was present
  *   before the call.  size: number of entries.  export: all entries of a bucket range.
@@ -83,6 +88,7 @@ typedef struct {
     uint32_t S;
     int mode, policy;
     uint64_t clock;
+    uint32_t subrounds; /* route sub-rounds per upsert call (1 = the whole batch at once) */
     ora_entry* e;  /* bucket b holds e[b*S .. b*S + cnt[b]) */
     uint32_t* cnt;
     /* path counters of the last calls (used for byte accounting) */
@@ -123,6 +129,7 @@ ora_table* ora_create(uint64_t B, uint32_t S, int mode, int policy) {
     t->S = S;
     t->mode = mode;
     t->policy = policy;
+    t->subrounds = 1;
     t->e = (ora_entry*)calloc(B * S, sizeof(ora_entry));
     t->cnt = (uint32_t*)calloc(B, sizeof(uint32_t));
     if (!t->e || !t->cnt) {
@@ -214,6 +221,7 @@ typedef struct {
 
 typedef struct {
     uint64_t key, bucket, s_new, vid;
+    uint64_t last; /* index of the key's last occurrence in the batch */
     long slot;  /* UPDATE: index in bucket at routing time */
     int kind;   /* 1 = UPDATE, 2 = INSERT */
     uint64_t inc;
@@ -225,6 +233,12 @@ static uint64_t dd_find(dd_slot* m, uint64_t mask, uint64_t key) {
     uint64_t p = ora_fmix64(key ^ 0x5bd1e995ULL) & mask;
     while (m[p].key != 0 && m[p].key != key) p = (p + 1) & mask;
     return p;
+}
+
+static int cmp_last(const void* pa, const void* pb) {
+    const ora_op* a = *(ora_op* const*)pa;
+    const ora_op* b = *(ora_op* const*)pb;
+    return a->last < b->last ? -1 : (a->last > b->last ? 1 : 0);
 }
 
 static int cmp_insert(const void* pa, const void* pb) {
@@ -275,80 +289,96 @@ static long upsert_core(ora_table* t, uint64_t n, const uint64_t* keys, const ui
         if (m[p].key == 0) continue;
         ora_op* o = &ops[m[p].op];
         o->key = m[p].key;
+        o->last = m[p].last;
         o->vid = vids[m[p].last];
         o->inc = m[p].inc;
         if (t->policy == ORA_CUSTOM) o->s_new = scores[m[p].last];
         else if (t->policy == ORA_LRU) o->s_new = t->clock;
         else o->s_new = m[p].inc;
     }
-    /* 3. route against the pre-batch table (routing writes nothing) */
-    for (long q = 0; q < nops; ++q) {
-        ora_op* o = &ops[q];
-        uint64_t b1 = ora_b1(t, o->key), b2 = ora_b2(t, o->key);
-        long j = find_in(t, b1, o->key);
-        if (j >= 0) {
-            o->kind = 1; o->bucket = b1; o->slot = j;
-            continue;
-        }
-        if (b2 != b1 && (j = find_in(t, b2, o->key)) >= 0) {
-            o->kind = 1; o->bucket = b2; o->slot = j;
-            continue;
-        }
-        o->kind = 2;
-        if (b1 == b2) {
-            o->bucket = b1;
-        } else if (t->cnt[b1] < t->S || t->cnt[b2] < t->S) { /* phase D1 */
-            o->bucket = (t->cnt[b1] <= t->cnt[b2]) ? b1 : b2;
-        } else { /* phase D2 */
-            const ora_entry* m1 = t->e + b1 * t->S + min_in(t, b1);
-            const ora_entry* m2 = t->e + b2 * t->S + min_in(t, b2);
-            o->bucket = entry_less(m2, m1) ? b2 : b1;
-            t->st_d2_routes++;
-        }
-    }
-    /* 4a. updates */
-    for (long q = 0; q < nops; ++q) {
-        ora_op* o = &ops[q];
-        if (o->kind != 1) continue;
-        ora_entry* e = t->e + o->bucket * t->S + o->slot;
-        if (t->policy == ORA_LFU) e->score = sat_add(e->score, o->inc);
-        else e->score = o->s_new;
-        if (!keep_found) e->vid = o->vid;
-        o->out_vid = e->vid;
-        o->status = ST_UPDATED;
-        t->st_upd++;
-    }
-    /* 4b. inserts, per bucket, by (score desc, key asc) */
+    /* operations in order of their key's last occurrence; chunk of rank q: q * r / N */
+    ora_op** ord = (ora_op**)malloc((size_t)(nops ? nops : 1) * sizeof(ora_op*));
     ora_op** ins = (ora_op**)malloc((size_t)(nops ? nops : 1) * sizeof(ora_op*));
-    long nins = 0;
-    for (long q = 0; q < nops; ++q)
-        if (ops[q].kind == 2) ins[nins++] = &ops[q];
-    qsort(ins, (size_t)nins, sizeof(ora_op*), cmp_insert);
+    ora_op** sel = (ora_op**)malloc((size_t)(nops ? nops : 1) * sizeof(ora_op*));
+    if (!ord || !ins || !sel) {
+        free(ord); free(ins); free(sel); free(m); free(ops);
+        return -1;
+    }
+    for (long q = 0; q < nops; ++q) ord[q] = &ops[q];
+    qsort(ord, (size_t)nops, sizeof(ora_op*), cmp_last);
+    const uint64_t r = t->subrounds ? t->subrounds : 1;
     long nev = 0;
-    for (long q = 0; q < nins; ++q) {
-        ora_op* o = ins[q];
-        uint64_t b = o->bucket;
-        o->out_vid = o->vid; /* inserted, or rejected: the key's own value-id */
-        ora_entry* be = t->e + b * t->S;
-        if (t->cnt[b] < t->S) {
-            ora_entry* e = be + t->cnt[b]++;
-            e->key = o->key; e->score = o->s_new; e->vid = o->vid;
-            o->status = ST_INSERTED;
-            t->st_ins++;
-            continue;
+    for (uint64_t c = 0; c < r; ++c) {
+        long nsel = 0;
+        for (long q = 0; q < nops; ++q)
+            if ((uint64_t)q * r / (uint64_t)nops == c) sel[nsel++] = ord[q];
+        /* 3. route against the table before this chunk (routing writes nothing) */
+        for (long q = 0; q < nsel; ++q) {
+            ora_op* o = sel[q];
+            uint64_t b1 = ora_b1(t, o->key), b2 = ora_b2(t, o->key);
+            long j = find_in(t, b1, o->key);
+            if (j >= 0) {
+                o->kind = 1; o->bucket = b1; o->slot = j;
+                continue;
+            }
+            if (b2 != b1 && (j = find_in(t, b2, o->key)) >= 0) {
+                o->kind = 1; o->bucket = b2; o->slot = j;
+                continue;
+            }
+            o->kind = 2;
+            if (b1 == b2) {
+                o->bucket = b1;
+            } else if (t->cnt[b1] < t->S || t->cnt[b2] < t->S) { /* phase D1 */
+                o->bucket = (t->cnt[b1] <= t->cnt[b2]) ? b1 : b2;
+            } else { /* phase D2 */
+                const ora_entry* m1 = t->e + b1 * t->S + min_in(t, b1);
+                const ora_entry* m2 = t->e + b2 * t->S + min_in(t, b2);
+                o->bucket = entry_less(m2, m1) ? b2 : b1;
+                t->st_d2_routes++;
+            }
         }
-        uint32_t mi = min_in(t, b);
-        if (o->s_new > be[mi].score) {
-            if (ev_keys) ev_keys[nev] = be[mi].key;
-            if (ev_vids) ev_vids[nev] = be[mi].vid;
-            if (ev_scores) ev_scores[nev] = be[mi].score;
-            nev++;
-            be[mi].key = o->key; be[mi].score = o->s_new; be[mi].vid = o->vid;
-            o->status = ST_INSERTED_EVICT;
-            t->st_evict++;
-        } else {
-            o->status = ST_REJECTED;
-            t->st_rej++;
+        /* 4a. updates */
+        for (long q = 0; q < nsel; ++q) {
+            ora_op* o = sel[q];
+            if (o->kind != 1) continue;
+            ora_entry* e = t->e + o->bucket * t->S + o->slot;
+            if (t->policy == ORA_LFU) e->score = sat_add(e->score, o->inc);
+            else e->score = o->s_new;
+            if (!keep_found) e->vid = o->vid;
+            o->out_vid = e->vid;
+            o->status = ST_UPDATED;
+            t->st_upd++;
+        }
+        /* 4b. inserts, per bucket, by (score desc, key asc) */
+        long nins = 0;
+        for (long q = 0; q < nsel; ++q)
+            if (sel[q]->kind == 2) ins[nins++] = sel[q];
+        qsort(ins, (size_t)nins, sizeof(ora_op*), cmp_insert);
+        for (long q = 0; q < nins; ++q) {
+            ora_op* o = ins[q];
+            uint64_t b = o->bucket;
+            o->out_vid = o->vid; /* inserted, or rejected: the key's own value-id */
+            ora_entry* be = t->e + b * t->S;
+            if (t->cnt[b] < t->S) {
+                ora_entry* e = be + t->cnt[b]++;
+                e->key = o->key; e->score = o->s_new; e->vid = o->vid;
+                o->status = ST_INSERTED;
+                t->st_ins++;
+                continue;
+            }
+            uint32_t mi = min_in(t, b);
+            if (o->s_new > be[mi].score) {
+                if (ev_keys) ev_keys[nev] = be[mi].key;
+                if (ev_vids) ev_vids[nev] = be[mi].vid;
+                if (ev_scores) ev_scores[nev] = be[mi].score;
+                nev++;
+                be[mi].key = o->key; be[mi].score = o->s_new; be[mi].vid = o->vid;
+                o->status = ST_INSERTED_EVICT;
+                t->st_evict++;
+            } else {
+                o->status = ST_REJECTED;
+                t->st_rej++;
+            }
         }
     }
     /* 5. per-occurrence status */
@@ -367,10 +397,18 @@ static long upsert_core(ora_table* t, uint64_t n, const uint64_t* keys, const ui
     }
     for (uint64_t i = 0; i < n; ++i)
         if (is_reserved(keys[i])) t->st_invalid++;
+    free(ord);
     free(ins);
+    free(sel);
     free(ops);
     free(m);
     return nev;
+}
+
+int ora_set_subrounds(ora_table* t, uint32_t r) {
+    if (!t || r < 1 || r > 64) return -1;
+    t->subrounds = r;
+    return 0;
 }
 
 long ora_upsert(ora_table* t, uint64_t n, const uint64_t* keys, const uint64_t* vids,

@@ -43,6 +43,7 @@ class PyTable:
         self.mode = mode
         self.policy = policy
         self.clock = 0
+        self.subrounds = 1  # route sub-rounds per upsert call
         self.buckets = [dict() for _ in range(n_buckets)]
 
     # --- hashing (Sec. 3.2; second hash of Alg. 3) ---
@@ -114,54 +115,60 @@ class PyTable:
                 s_new[k] = self.clock
             else:
                 s_new[k] = inc[k]
-        # routing sees the table before the batch
-        snap_len = [len(b) for b in self.buckets]
-        snap_min = {}
-        updates, inserts = [], {}
-        for k in order:
-            b = self._where(k)
-            if b is not None:
-                updates.append((b, k))
-                continue
-            b1, b2 = self.candidates(k)
-            if b1 == b2:
-                tgt = b1
-            elif snap_len[b1] < self.S or snap_len[b2] < self.S:  # phase D1: load
-                tgt = b1 if snap_len[b1] <= snap_len[b2] else b2
-            else:  # phase D2: the lower minimum (score, key)
-                for b in (b1, b2):
-                    if b not in snap_min:
-                        snap_min[b] = self._min_entry(self.buckets[b])
-                tgt = b2 if snap_min[b2] < snap_min[b1] else b1
-            inserts.setdefault(tgt, []).append(k)
+        # sub-rounds: operations ordered by their key's last occurrence, rank q in chunk q*r//N;
+        # each chunk routes against the table the chunks before it left
+        by_last = sorted(order, key=lambda x: last[x])
+        r = self.subrounds
         status, out = {}, {}
-        for b, k in updates:
-            ent = self.buckets[b][k]
-            if self.policy == LFU:
-                ent[0] = min(M64, ent[0] + inc[k])
-            else:
-                ent[0] = s_new[k]
-            if not keep_found:
-                ent[1] = vids[last[k]]
-            out[k] = ent[1]
-            status[k] = UPDATED
         evicted = []
-        for b in sorted(inserts):
-            bucket = self.buckets[b]
-            for k in sorted(inserts[b], key=lambda x: (-s_new[x], x)):
-                out[k] = vids[last[k]]
-                if len(bucket) < self.S:
-                    bucket[k] = [s_new[k], vids[last[k]]]
-                    status[k] = INSERTED
+        for c in range(r):
+            chunk = [k for q, k in enumerate(by_last) if q * r // len(by_last) == c]
+            # routing sees the table before the chunk
+            snap_len = [len(b) for b in self.buckets]
+            snap_min = {}
+            updates, inserts = [], {}
+            for k in chunk:
+                b = self._where(k)
+                if b is not None:
+                    updates.append((b, k))
                     continue
-                mscore, mkey = self._min_entry(bucket)
-                if s_new[k] > mscore:
-                    sc, vid = bucket.pop(mkey)
-                    evicted.append((mkey, sc, vid))
-                    bucket[k] = [s_new[k], vids[last[k]]]
-                    status[k] = INSERTED_EVICT
+                b1, b2 = self.candidates(k)
+                if b1 == b2:
+                    tgt = b1
+                elif snap_len[b1] < self.S or snap_len[b2] < self.S:  # phase D1: load
+                    tgt = b1 if snap_len[b1] <= snap_len[b2] else b2
+                else:  # phase D2: the lower minimum (score, key)
+                    for b in (b1, b2):
+                        if b not in snap_min:
+                            snap_min[b] = self._min_entry(self.buckets[b])
+                    tgt = b2 if snap_min[b2] < snap_min[b1] else b1
+                inserts.setdefault(tgt, []).append(k)
+            for b, k in updates:
+                ent = self.buckets[b][k]
+                if self.policy == LFU:
+                    ent[0] = min(M64, ent[0] + inc[k])
                 else:
-                    status[k] = REJECTED
+                    ent[0] = s_new[k]
+                if not keep_found:
+                    ent[1] = vids[last[k]]
+                out[k] = ent[1]
+                status[k] = UPDATED
+            for b in sorted(inserts):
+                bucket = self.buckets[b]
+                for k in sorted(inserts[b], key=lambda x: (-s_new[x], x)):
+                    out[k] = vids[last[k]]
+                    if len(bucket) < self.S:
+                        bucket[k] = [s_new[k], vids[last[k]]]
+                        status[k] = INSERTED
+                        continue
+                    mscore, mkey = self._min_entry(bucket)
+                    if s_new[k] > mscore:
+                        sc, vid = bucket.pop(mkey)
+                        evicted.append((mkey, sc, vid))
+                        bucket[k] = [s_new[k], vids[last[k]]]
+                        status[k] = INSERTED_EVICT
+                    else:
+                        status[k] = REJECTED
         st = [INVALID_KEY if k in (EMPTY, LOCKED) else status[k] for k in keys]
         return st, evicted, out
 

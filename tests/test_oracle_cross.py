@@ -18,10 +18,12 @@ def _c_state(o):
     return {b: sorted(x) for b, x in out.items()}
 
 
-def _run(seed, B, S, mode, policy, n_batches=25):
+def _run(seed, B, S, mode, policy, n_batches=25, subrounds=1):
     rng = random.Random(seed)
     c = oracle.Oracle(B, S, mode, policy)
     p = pyoracle.PyTable(B, S, mode, policy)
+    c.set_subrounds(subrounds)
+    p.subrounds = subrounds
     universe = [rng.getrandbits(64) | 1 for _ in range(B * S * 2)]
     universe += [0, M64]  # reserved words show up as invalid keys
     vid = 0
@@ -95,6 +97,14 @@ def test_c_and_python_oracles_agree(mode, policy, shape):
     B, S = shape
     for seed in range(6):
         _run(1000 * seed + 17 * B + S + 5 * policy + mode, B, S, mode, policy)
+
+
+@pytest.mark.parametrize("subrounds", [2, 3, 64])
+@pytest.mark.parametrize("policy", [oracle.CUSTOM, oracle.LRU, oracle.LFU])
+def test_c_and_python_oracles_agree_with_subrounds(policy, subrounds):
+    for seed in range(4):
+        for B, S in [(2, 4), (4, 8)]:
+            _run(7000 * seed + 31 * subrounds + 5 * policy + B, B, S, oracle.DUAL, policy, subrounds=subrounds)
 
 
 def test_lfu_saturates():
