@@ -738,6 +738,20 @@ def main():
                     best = max(best, timed(lambda: t.find(q, values_out=outs, found_out=found, want_scores=False)))
                 r[f"find_nodigest_hit{h}_bkvs"] = best
                 t.set_tuning(find_digest=1, find_group=tu["find_group"])
+            # the same fresh-key insert_or_assign with 4 route sub-rounds (erased again below load 1)
+            fk4 = gen_keys(860 + li, batch, 0, device=dev)
+            t.set_route_subrounds(4)
+            t.workspace(cskv.OP_INSERT_OR_ASSIGN, batch)  # grown before the timed call
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t.insert_or_assign(fk4, rows, status_out=status)
+            e1.record()
+            torch.cuda.synchronize()
+            t.set_route_subrounds(1)
+            r["insert_or_assign_subrounds4_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
+            if lv.target < 1.0:
+                t.erase(fk4, erased_out=erased)
             # find_or_insert of half resident, half fresh keys; the fresh ones are erased again
             fk = torch.cat([q100[li][: batch // 2], gen_keys(850 + li, batch - batch // 2, 0, device=dev)])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

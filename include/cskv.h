@@ -281,6 +281,21 @@ int cskv_set_tuning(cskv_table* table, int param, int value);
 int cskv_get_tuning(const cskv_table* table, int param);
 
 /*
+ * Route sub-rounds (a semantic setting of the upsert calls: insert_or_assign, insert_and_evict,
+ * find_or_insert; default 1).  Within one call every key routes against the table as it was
+ * before the call (Alg. 3's occupancy and minimum tests see no key of the same call), which
+ * leaves large batches less evenly spread than the paper's one-key-at-a-time picture.  With r
+ * sub-rounds a call's distinct keys, ordered by the index of their last occurrence, are cut into
+ * r chunks (rank q of N goes to chunk floor(q * r / N)); chunk after chunk is routed and applied
+ * against the table the chunks before it left.  Statuses, scores (one LRU clock per call),
+ * dedupe and LFU sums stay per call.  r = 1..64, else CSKV_EINVAL.  The workspace an upsert needs
+ * grows with r > 1 (query cskv_workspace_bytes after setting it); a program built before a change
+ * refuses to launch (CSKV_EINVAL) until it is rebuilt.
+ */
+int cskv_set_route_subrounds(cskv_table* table, uint32_t rounds);
+uint32_t cskv_get_route_subrounds(const cskv_table* table);
+
+/*
  * Concurrent calls from several host threads and streams (Sec. 3.5, the three operation groups
  * and their compatibility table; Sec. 4.4, the host/device lock).  Roles: readers = find,
  * contains, find_ptr, size, export, export_if and programs without writes; updaters = assign,

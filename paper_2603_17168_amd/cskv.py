@@ -86,6 +86,8 @@ def lib():
         "cskv_policy": (I, [P]),
         "cskv_strerror": (ctypes.c_char_p, [I]),
         "cskv_set_lock_mode": (I, [P, I]),
+        "cskv_set_route_subrounds": (I, [P, U32]),
+        "cskv_get_route_subrounds": (U32, [P]),
         "cskv_table_bytes_tiered": (SZ, [U64, U32, U32, U64]),
         "cskv_host_value_bytes": (SZ, [U64, U32, U64]),
         "cskv_create_tiered": (I, [ctypes.POINTER(P), U64, U32, U32, I, I, P, SZ, U64, P, SZ, P]),
@@ -203,6 +205,16 @@ class Table:
 
     def get_tuning(self) -> dict:
         return {k: int(lib().cskv_get_tuning(self._h, v)) for k, v in TUNE.items()}
+
+    def set_route_subrounds(self, rounds: int):
+        """Route sub-rounds per upsert call (1..64): the call's distinct keys, ordered by last
+        occurrence, are routed and applied in that many chunks, each against the table the
+        chunks before it left.  Results depend on it (unlike the tuning knobs)."""
+        _check(lib().cskv_set_route_subrounds(self._h, int(rounds)), f"cskv_set_route_subrounds({rounds})")
+
+    @property
+    def route_subrounds(self) -> int:
+        return int(lib().cskv_get_route_subrounds(self._h))
 
     def row_address(self, slot: int) -> int:
         """Device address of the value row of slot e = bucket * 128 + slot (a device alias of host

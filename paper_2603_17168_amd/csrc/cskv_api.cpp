@@ -34,7 +34,7 @@ static uint32_t inline_capacity(uint64_t n, uint64_t nb) {
     return c;
 }
 
-UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
+UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds) {
     UpsertLayout L;
     uint64_t P = 64;
     int logP = 6;
@@ -62,6 +62,8 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb) {
     L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
     L.off_touched = o; o = align256(o + nslow * 4);
+    L.off_rank = o;    o = align256(o + (rounds > 1 ? n * 4 : 0));
+    L.off_bsum = o;    o = align256(o + (rounds > 1 ? ((n + 255) / 256) * 4 : 0));
     L.list_mode = n * 4 <= nb;  // apply visits only the touched buckets (route lists them)
     L.total = o;
     return L;
@@ -166,6 +168,7 @@ int cskv_create_tiered(cskv_table** out, uint64_t capacity, uint32_t bucket_size
     t->blocks_per_cu = 0;
     t->find_pairs = 0;
     t->find_digest = 1;
+    t->subrounds = 1;
     t->roles = new (std::nothrow) TableLock();
     if (!t->roles) {
         delete t;
@@ -207,7 +210,7 @@ size_t cskv_workspace_bytes(const cskv_table* table, int op, uint64_t n) {
         case CSKV_OP_INSERT_OR_ASSIGN:
         case CSKV_OP_INSERT_AND_EVICT:
         case CSKV_OP_ASSIGN:
-        case CSKV_OP_FIND_OR_INSERT: return upsert_layout(n, table->view.nbuckets).total;
+        case CSKV_OP_FIND_OR_INSERT: return upsert_layout(n, table->view.nbuckets, table->subrounds).total;
         case CSKV_OP_ERASE: return erase_ws_bytes(n);
         default: return 0;
     }
@@ -245,7 +248,7 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     if (!aligned(a.keys, 8) || (a.vals && !aligned(a.vals, 16)) || !aligned(d_ws, 256) ||
         (a.scores && !aligned(a.scores, 8)) || (a.out && !aligned(a.out, 16)))
         return CSKV_EINVAL;
-    const UpsertLayout L = upsert_layout(n, table->view.nbuckets);
+    const UpsertLayout L = upsert_layout(n, table->view.nbuckets, table->subrounds);
     if (ws_bytes < L.total) return CSKV_ENOMEM;
     uint8_t* b = reinterpret_cast<uint8_t*>(d_ws);
     UpsertWs& w = *out;
@@ -260,6 +263,10 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     w.ol = reinterpret_cast<OpEntry*>(b + L.off_ol);
     w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);
     w.touched = reinterpret_cast<uint32_t*>(b + L.off_touched);
+    w.rank = reinterpret_cast<uint32_t*>(b + L.off_rank);
+    w.bsum = reinterpret_cast<uint32_t*>(b + L.off_bsum);
+    w.rounds = (int)table->subrounds;
+    w.round = 0;
     w.P = L.P;
     w.logP = L.logP;
     w.cap = L.cap;
@@ -460,6 +467,14 @@ int cskv_get_tuning(const cskv_table* table, int param) {
         default: return -1;
     }
 }
+
+int cskv_set_route_subrounds(cskv_table* table, uint32_t rounds) {
+    if (!table || rounds < 1 || rounds > 64) return CSKV_EINVAL;
+    table->subrounds = rounds;
+    return CSKV_OK;
+}
+
+uint32_t cskv_get_route_subrounds(const cskv_table* table) { return table ? table->subrounds : 0; }
 
 int cskv_set_lock_mode(cskv_table* table, int mode) {
     if (!table || (mode != CSKV_LOCK_NONE && mode != CSKV_LOCK_TRIPLE_GROUP && mode != CSKV_LOCK_READER_WRITER))

@@ -35,7 +35,8 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint8_t kInsertSlot = 0xFF;
 constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
-enum Counter { kCtrSlow = 0, kCtrTouched = 1, kCtrDup = 2 };  // kCtrDup: the call repeats a key
+// kCtrDup: the call repeats a key; kCtrDistinct: its number of distinct keys (sub-rounds only)
+enum Counter { kCtrSlow = 0, kCtrTouched = 1, kCtrDup = 2, kCtrDistinct = 3 };
 
 struct TableView {
     uint8_t* dig;
@@ -84,11 +85,15 @@ struct UpsertWs {
     OpEntry* ol;
     uint32_t* slow;
     uint32_t* touched;
+    uint32_t* rank;  // sub-rounds: rank of each last occurrence among them, in input order
+    uint32_t* bsum;  // sub-rounds: per-block counts of last occurrences, then their offsets
     uint64_t P;
     int logP;
     uint32_t cap;    // inline operations per bucket
     int list_mode;   // apply visits only the touched buckets (small batches)
     float* out;      // find_or_insert: rows returned per occurrence (resident rows are kept); else null
+    int rounds;      // route sub-rounds of the call (1: the whole batch routes at once)
+    int round;       // the sub-round a route / apply launch serves
 };
 
 // one batch of a merged run of finds (reader group): keys [begin, begin + n) of the run
@@ -122,7 +127,7 @@ struct StorageLayout {
 
 struct UpsertLayout {
     size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_zero_end, off_zero_end_lfu;
-    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, off_touched, total;
+    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, off_touched, off_rank, off_bsum, total;
     uint64_t P;
     int logP;
     uint32_t cap;
@@ -130,7 +135,7 @@ struct UpsertLayout {
 };
 
 StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim, uint64_t hbm_rows);
-UpsertLayout upsert_layout(uint64_t n, uint64_t nbuckets);
+UpsertLayout upsert_layout(uint64_t n, uint64_t nbuckets, uint32_t rounds = 1);
 size_t erase_ws_bytes(uint64_t n);
 
 // launchers (return hipError_t of the last launch)
@@ -158,6 +163,9 @@ hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n
 hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals,
                                const EvictOut& ev, hipStream_t s);
 hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, uint32_t dim, hipStream_t s);
+// route + apply of every sub-round (w.rounds > 1), after launch_upsert_prep
+hipError_t launch_upsert_rounds(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                                const float* vals, const uint64_t* scores, const EvictOut& ev, int group, hipStream_t s);
 hipError_t launch_erase_probe(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                               uint32_t* ws_slot, int group, hipStream_t s);
 hipError_t launch_erase_clear(const TableView& t, uint64_t n, uint32_t* ws_slot, hipStream_t s);
@@ -216,6 +224,7 @@ struct cskv_table {
     int blocks_per_cu;  // persistent grid of merged find runs: blocks per compute unit (0 = one group per key)
     int find_pairs;     // find: two keys per lane group
     int find_digest;    // find: 1 = digest-filtered probes, 0 = the no-digest ablation
+    uint32_t subrounds; // route sub-rounds per upsert call (a semantic setting, 1 by default)
     int num_cus;
     int device;  // HIP device the table lives on
     cskv::TableLock* roles = nullptr;  // role lock across host threads and streams (off in lock mode none)

@@ -84,6 +84,7 @@ struct cskv_program {
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraph_t> children;  // per-phase graphs of the overlapped form's graph
     bool ready = false;
+    uint32_t subrounds = 1;  // the table's route sub-rounds when the phases were built
     int overlap = 0;  // 0: one stream; 1: phase graph on reader / writer / prep streams; 2: prep ahead
     hipStream_t lane[kLanes] = {};
     std::vector<hipEvent_t> events;  // one per phase, then the fork event
@@ -226,9 +227,14 @@ static void build_phases(cskv_program* p) {
             continue;
         }
         const int prep = add(kPhPrep, kLanePrep + j, s, j, entry);
-        const int route = add(kPhRoute, kLaneWrite, s, j, {prep, last_writer});
-        readers.push_back(route);
-        std::vector<int> w = readers;
+        std::vector<int> w;
+        if (p->table->subrounds == 1) {  // routing reads the table beside the running readers
+            const int route = add(kPhRoute, kLaneWrite, s, j, {prep, last_writer});
+            readers.push_back(route);
+        } else {  // sub-rounds: every round's routing runs inside the apply phase
+            w.push_back(prep);
+        }
+        w.insert(w.end(), readers.begin(), readers.end());
         w.push_back(last_writer);
         const int apply = add(kPhApply, kLaneWrite, s, j, w);
         readers.clear();
@@ -270,7 +276,8 @@ static size_t scratch_need(const cskv_program* p) {
     for (const Op& o : p->ops) {
         if (o.n == 0) continue;
         size_t b = 0;
-        if (o.kind == kUpsert || o.kind == kUpsertEvict) b = upsert_layout(o.n, p->table->view.nbuckets).total;
+        if (o.kind == kUpsert || o.kind == kUpsertEvict)
+            b = upsert_layout(o.n, p->table->view.nbuckets, p->table->subrounds).total;
         else if (o.kind == kErase) b = erase_ws_bytes(o.n);
         if (b > need) need = b;
     }
@@ -395,6 +402,7 @@ size_t cskv_program_workspace_bytes(const cskv_program* p) {
 int cskv_program_set_workspace(cskv_program* p, void* d_ws, size_t ws_bytes) {
     if (!p || p->ready || !d_ws || !aligned(d_ws, 256)) return CSKV_EINVAL;
     if (ws_bytes < cskv_program_workspace_bytes(p)) return CSKV_ENOMEM;
+    p->subrounds = p->table->subrounds;
     find_hazards(p);
     build_plan(p);
     p->ws = reinterpret_cast<uint8_t*>(d_ws);
@@ -475,8 +483,15 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
     if (rc != CSKV_OK) return rc;
     switch (ph.kind) {
         case kPhPrep: e = launch_upsert_prep(t->view, w, a.n, a.keys, a.scores, a.ev, zero_bytes, s); break;
-        case kPhRoute: e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, t->route_group, s); break;
-        case kPhApply: e = launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s); break;
+        // with route sub-rounds every round routes after the previous one applied: all of it runs
+        // in the apply phase (on the writer lane, after the concurrent readers)
+        case kPhRoute:
+            if (w.rounds == 1) e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, t->route_group, s);
+            break;
+        case kPhApply:
+            e = w.rounds == 1 ? launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s)
+                              : launch_upsert_rounds(t->view, w, a.n, a.keys, a.vals, a.scores, a.ev, t->route_group, s);
+            break;
         default: e = launch_upsert_finish(w, a.n, a.status, t->view.dim, s); break;
     }
     return e == hipSuccess ? CSKV_OK : CSKV_EHIP;
@@ -545,8 +560,11 @@ static int program_role(const cskv_program* p) {
 
 extern "C" {
 
+// the table's route sub-rounds changed since set_workspace: phases and scratch no longer fit
+static bool stale(const cskv_program* p) { return p->table->subrounds != p->subrounds; }
+
 int cskv_program_launch(cskv_program* p, void* stream) {
-    if (!p || !p->ready) return CSKV_EINVAL;
+    if (!p || !p->ready || stale(p)) return CSKV_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RoleScope role(p->table, program_role(p), s);
     if (!role.ok()) return CSKV_EHIP;
@@ -554,7 +572,7 @@ int cskv_program_launch(cskv_program* p, void* stream) {
 }
 
 int cskv_program_capture(cskv_program* p, void* stream) {
-    if (!p || !p->ready || !stream) return CSKV_EINVAL;
+    if (!p || !p->ready || !stream || stale(p)) return CSKV_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     drop_graph(p);
     int rc;
@@ -574,7 +592,7 @@ int cskv_program_capture(cskv_program* p, void* stream) {
 }
 
 int cskv_program_replay(cskv_program* p, void* stream) {
-    if (!p || !p->ready || !p->exec) return CSKV_EINVAL;
+    if (!p || !p->ready || !p->exec || stale(p)) return CSKV_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RoleScope role(p->table, program_role(p), s);
     if (!role.ok()) return CSKV_EHIP;

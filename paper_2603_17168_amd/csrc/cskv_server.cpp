@@ -53,7 +53,8 @@ extern "C" {
 
 size_t cskv_serve_workspace_bytes(const cskv_table* table, uint64_t max_request_keys, uint64_t arena_budget_bytes) {
     if (!table) return 0;
-    return align256(upsert_layout(max_request_keys, table->view.nbuckets).total) + align256(arena_budget_bytes);
+    return align256(upsert_layout(max_request_keys, table->view.nbuckets, table->subrounds).total) +
+           align256(arena_budget_bytes);
 }
 
 int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const cskv_serve_config* cfg, void* d_ws,
@@ -72,7 +73,7 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
             return CSKV_EINVAL;
         if (r.n > max_n) max_n = r.n;
     }
-    const size_t ups_bytes = align256(upsert_layout(max_n, t->view.nbuckets).total);
+    const size_t ups_bytes = align256(upsert_layout(max_n, t->view.nbuckets, t->subrounds).total);
     if (ws_bytes < ups_bytes + align256(cfg->arena_budget_bytes)) return CSKV_ENOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     RoleScope role(t, kInserter, s);  // the whole trace holds the table as one inserter

@@ -104,6 +104,65 @@ __global__ void __launch_bounds__(256) k_dedupe(TableView t, UpsertWs w, uint64_
 }
 
 // ------------------------------------------------------------------------------------------
+// route sub-rounds: the distinct keys, ordered by the index of their last occurrence, are cut
+// into `rounds` chunks (rank q goes to chunk q * rounds / N); each chunk is routed and applied
+// against the table the chunks before it left.  The ranks come from a three-kernel scan of the
+// last-occurrence flags (block counts, one block scanning them, in-block offsets by ballot).
+__device__ __forceinline__ bool last_occurrence(const UpsertWs& w, uint64_t i, bool dups) {
+    const uint32_t p = w.slot_of[i];
+    if (p == kNoSlot) return false;
+    if (!dups) return true;
+    const DedupeEntry de = w.dd[p];
+    return (de.claim > de.last ? de.claim : de.last) == (uint32_t)(i + 1);
+}
+
+__global__ void __launch_bounds__(256) k_rank_count(UpsertWs w, uint64_t n) {
+    __shared__ uint32_t part[4];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool dups = w.ctr[kCtrDup] != 0;
+    const uint64_t bal = __ballot(i < n && last_occurrence(w, i, dups));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) w.bsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ void __launch_bounds__(256) k_rank_scan(UpsertWs w, uint64_t nblk) {
+    __shared__ uint32_t buf[256];
+    uint32_t carry = 0;
+    for (uint64_t base = 0; base < nblk; base += 256) {
+        const uint64_t j = base + threadIdx.x;
+        const uint32_t v = j < nblk ? w.bsum[j] : 0u;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive scan in LDS
+            const uint32_t x = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (j < nblk) w.bsum[j] = carry + buf[threadIdx.x] - v;  // exclusive offsets
+        carry += buf[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) w.ctr[kCtrDistinct] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_rank_write(UpsertWs w, uint64_t n) {
+    __shared__ uint32_t part[4];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool dups = w.ctr[kCtrDup] != 0;
+    const bool f = i < n && last_occurrence(w, i, dups);
+    const uint64_t bal = __ballot(f);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) part[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = w.bsum[blockIdx.x];
+    for (int q = 0; q < (int)(threadIdx.x >> 6); ++q) off += part[q];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (f) w.rank[i] = off + (uint32_t)__popcll(bal & below);
+}
+
+// ------------------------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
                                                const uint64_t* __restrict__ scores) {
@@ -116,6 +175,10 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     if (dups) {
         const DedupeEntry de = w.dd[p];
         if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    }
+    if (w.rounds > 1) {  // only the keys of this sub-round's chunk
+        const uint64_t nd = w.ctr[kCtrDistinct];
+        if ((uint64_t)w.rank[i] * (uint64_t)w.rounds / nd != (uint64_t)w.round) return;
     }
     const uint64_t k = keys[i];
     const uint64_t clock = *t.clock + 1;  // LRU: this call's clock (advanced after routing)
@@ -453,7 +516,8 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     __shared__ unsigned long long ev_base_s;
 
     const int lane = threadIdx.x;
-    if (blockIdx.x == 0 && lane == 0 && t.policy == 1) *t.clock += 1;  // routing has read the clock
+    // routing has read the clock (every sub-round of the call reads the same value)
+    if (blockIdx.x == 0 && lane == 0 && t.policy == 1 && w.round == w.rounds - 1) *t.clock += 1;
     const uint32_t nslow = w.ctr[kCtrSlow];
     const uint32_t chunks = t.dim >> 2;
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -745,13 +809,38 @@ hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, 
     return hipGetLastError();
 }
 
+hipError_t launch_upsert_rounds(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
+                                const float* vals, const uint64_t* scores, const EvictOut& ev, int group, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t nblk = (n + 255) / 256;
+    k_rank_count<<<(unsigned)nblk, 256, 0, s>>>(w, n);
+    k_rank_scan<<<1, 256, 0, s>>>(w, nblk);
+    k_rank_write<<<(unsigned)nblk, 256, 0, s>>>(w, n);
+    hipError_t e = hipGetLastError();
+    UpsertWs wr = w;
+    for (int c = 0; c < w.rounds && e == hipSuccess; ++c) {
+        wr.round = c;
+        if (c > 0) {  // the previous round's overflow lists and slow / touched cursors
+            if ((e = launch_fill_zero(w.okey, w.P * 8, s)) != hipSuccess) break;
+            if ((e = launch_fill_zero(w.ctr + kCtrSlow, 2 * sizeof(uint32_t), s)) != hipSuccess) break;
+        }
+        if ((e = launch_upsert_route(t, wr, n, keys, scores, group, s)) != hipSuccess) break;
+        e = launch_upsert_apply(t, wr, n, vals, ev, s);
+    }
+    return e;
+}
+
 hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
                          const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
                          hipStream_t s) {
     hipError_t e;
     if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
-    if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
-    if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
+    if (w.rounds > 1) {
+        if ((e = launch_upsert_rounds(t, w, n, keys, vals, scores, ev, group, s)) != hipSuccess) return e;
+    } else {
+        if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
+        if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
+    }
     return launch_upsert_finish(w, n, status, t.dim, s);
 }
 

@@ -47,8 +47,10 @@ UNIVERSE_FACTOR = 10
 class GpuTable:
     """The experiment interface over a cskv.Table (value rows of dim 4, all zero)."""
 
-    def __init__(self, capacity: int, mode: str, policy: str, device="cuda"):
+    def __init__(self, capacity: int, mode: str, policy: str, device="cuda", subrounds: int = 1):
         self.t = cskv.Table(capacity, 4, mode=mode, policy=policy, device=device)
+        if subrounds != 1:
+            self.t.set_route_subrounds(subrounds)
         self._zero = torch.zeros((0, 4), dtype=torch.float32, device=self.t.device)
 
     def _rows(self, n):
@@ -216,6 +218,12 @@ def main():
         res["first_eviction_dual_by_batch"][str(1 << lb)] = round(
             first_eviction(GpuTable(cap, "dual", "custom"), cap, 1 << lb, dev=dev), 4)
     log(f"first eviction dual by batch: {res['first_eviction_dual_by_batch']}")
+    # route sub-rounds at the ingestion batch size: each chunk sees the occupancies the chunks
+    # before it left
+    res["first_eviction_dual_by_subrounds"] = {
+        str(r): round(first_eviction(GpuTable(cap, "dual", "custom", subrounds=r), cap, args.batch, dev=dev), 4)
+        for r in (1, 2, 4, 8, 16)}
+    log(f"first eviction dual at batch {args.batch} by sub-rounds: {res['first_eviction_dual_by_subrounds']}")
     res["zipf0.99_lru"] = {}
     for m in ("single", "dual"):
         r = zipf_ingestion(GpuTable(cap, m, "lru"), cap, 0.99, "lru", args.batch, args.capacities, dev=dev,
