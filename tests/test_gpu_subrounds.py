@@ -9,7 +9,6 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
 from paper_2603_17168_amd import cskv
 from paper_2603_17168_amd.workload import as_u64, batch_schedule, keys as gen_keys, program_inputs
 from tests.parity import Twin

@@ -7,7 +7,6 @@ import sys
 
 import numpy as np
 import pytest
-import torch
 
 from paper_2603_17168_amd.workload import as_u64, keys as gen_keys
 from tests.parity import Twin
