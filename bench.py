@@ -266,19 +266,11 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
     def outputs():
         return [(d["flag"].clone(), d["out"][d["flag"].bool()].clone() if "out" in d else None) for d in ops]
 
-    def best_of(fn, sync, reps=3):
-        """min wall time of `reps` runs from the same starting table (after one warm run)"""
-        best = float("inf")
-        for r in range(reps + 1):
-            restore()
-            t0 = time.perf_counter()
-            fn()
-            sync()
-            if r:
-                best = min(best, time.perf_counter() - t0)
-        return best
-
-    res = {"plain_s": best_of(run_plain, torch.cuda.synchronize)}
+    # every form from the same starting table, interleaved round by round (so that clock and
+    # thermal drift fall on all forms alike); best of three timed rounds after a warm one
+    restore()
+    run_plain()
+    torch.cuda.synchronize()
     ref = outputs()
 
     def build(overlap):
@@ -293,20 +285,36 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
                 pr.add_erase(d["keys"], d["flag"])
         return pr.finalize()
 
-    same = True
-    prog = None
+    def same_as_ref():
+        return all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
+                   for a, b in zip(ref, outputs()))
+
+    forms = {"plain_s": (run_plain, torch.cuda.synchronize)}
+    progs = []
+    stream = torch.cuda.Stream(device=dev)
     for overlap in (0, 1, 2):
         tag = {0: "", 1: "_overlapped", 2: "_prep_ahead"}[overlap]
         prog = build(overlap)
-        res["program" + tag] = best_of(prog.launch, torch.cuda.synchronize)
-        same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
-                            for a, b in zip(ref, outputs()))
-        stream = torch.cuda.Stream(device=dev)
         prog.capture(stream)
-        res["graph" + tag] = best_of(lambda: prog.replay(stream), stream.synchronize)
-        same = same and all(torch.equal(a[0], b[0]) and (a[1] is None or torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))
-                            for a, b in zip(ref, outputs()))
-        log(f"batched overlap={overlap}: program {res['program' + tag] * 1e3:.2f} ms, graph {res['graph' + tag] * 1e3:.2f} ms")
+        progs.append(prog)
+        forms["program" + tag] = (prog.launch, torch.cuda.synchronize)
+        forms["graph" + tag] = ((lambda p_: (lambda: p_.replay(stream)))(prog), stream.synchronize)
+    res = {k: float("inf") for k in forms}
+    same = True
+    for r in range(4):
+        for k, (fn, sync) in forms.items():
+            restore()
+            t0 = time.perf_counter()
+            fn()
+            sync()
+            if r:
+                res[k] = min(res[k], time.perf_counter() - t0)
+            if r == 1 and k != "plain_s":
+                same = same and same_as_ref()
+    for overlap, tag in ((0, ""), (1, "_overlapped"), (2, "_prep_ahead")):
+        log(f"batched overlap={overlap}: plain {res['plain_s'] * 1e3:.2f} ms, program {res['program' + tag] * 1e3:.2f} ms, "
+            f"graph {res['graph' + tag] * 1e3:.2f} ms")
+    prog = progs[0]
     out = {"workload": f"{nbatches} batches log-uniform {lo}..{hi} keys, 70/25/5 find/insert_or_assign/erase, "
                        f"2^{log2_cap} slots dim {dim} LRU at load {load}",
            "total_keys": total, "segments": prog.segments,
@@ -319,7 +327,7 @@ def bench_batched(dev, log2_cap=26, dim=32, load=0.9, nbatches=256, lo=1 << 10, 
            "graph_prep_ahead_bkvs": round(total / res["graph_prep_ahead"] / 1e9, 3),
            "graph_vs_plain": round(res["plain_s"] / res["graph"], 3),
            "identical_outputs": bool(same), "tuning": tuning}
-    del prog, base, snap, ops
+    del prog, progs, base, snap, ops
     torch.cuda.empty_cache()
     return out
 

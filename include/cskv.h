@@ -343,7 +343,8 @@ int cskv_set_clock(cskv_table* table, uint64_t clock);
  *    CSKV_TUNE_FIND_BLOCKS_PER_CU > 0), with the table's tuning at the time the run's first
  *    find was added; a find whose buffers overlap an output of a find already in the run
  *    starts a new run;
- *  - every upsert or erase is a serialization point (inserter group) run as its usual kernels.
+ *  - every upsert or erase is a serialization point (inserter group) run as its usual kernels,
+ *    in the launch shapes (route and probe lanes) the table had when it was added.
  * All pointers are recorded at add time and must stay valid (and unchanged in size) while the
  * program is launched or replayed.  The program needs a device workspace of
  * cskv_program_workspace_bytes bytes (256-byte aligned), given once with

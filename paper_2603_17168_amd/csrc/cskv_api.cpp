@@ -276,23 +276,23 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     return CSKV_OK;
 }
 
-int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream, int group) {
     UpsertWs w;
     size_t zero_bytes = 0;
     const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes);
     if (rc != CSKV_OK || a.n == 0) return rc;
     return hip_rc(launch_upsert(table->view, w, a.n, a.keys, a.vals, a.scores, a.status, a.ev, zero_bytes,
-                                table->route_group, stream));
+                                group > 0 ? group : table->route_group, stream));
 }
 
 int enqueue_erase(cskv_table* table, uint64_t n, const uint64_t* d_keys, uint8_t* d_erased, void* d_ws,
-                  size_t ws_bytes, hipStream_t stream) {
+                  size_t ws_bytes, hipStream_t stream, int group) {
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
     if (!d_keys || !d_ws || !aligned(d_keys, 8) || !aligned(d_ws, 256)) return CSKV_EINVAL;
     if (ws_bytes < erase_ws_bytes(n)) return CSKV_ENOMEM;
-    return hip_rc(launch_erase(table->view, n, d_keys, d_erased, reinterpret_cast<uint32_t*>(d_ws), table->group,
-                               stream));
+    return hip_rc(launch_erase(table->view, n, d_keys, d_erased, reinterpret_cast<uint32_t*>(d_ws),
+                               group > 0 ? group : table->group, stream));
 }
 
 }  // namespace cskv

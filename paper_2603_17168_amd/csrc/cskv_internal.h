@@ -259,7 +259,8 @@ namespace cskv {
 // validates an upsert and lays out its workspace (CSKV_* code)
 int plan_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, UpsertWs* w, size_t* zero_bytes,
                 bool need_vals = true);
-int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
+// group: lanes per key of the routing (upsert) or probe (erase) kernel; -1 = the table's setting
+int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s, int group = -1);
 int enqueue_erase(cskv_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased, void* ws, size_t ws_bytes,
-                  hipStream_t s);
+                  hipStream_t s, int group = -1);
 }  // namespace cskv

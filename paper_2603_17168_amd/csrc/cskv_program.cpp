@@ -27,7 +27,8 @@ struct Op {
     uint8_t* flags;       // found / status / erased
     uint64_t* scores_out;
     EvictOut ev;
-    int group, prefetch, blocks_per_cu;  // tuning snapshot (finds)
+    int group, prefetch, blocks_per_cu;  // tuning snapshot: find and erase-probe shapes
+    int route_group;                     // tuning snapshot: upsert routing shape
 };
 
 struct Segment {
@@ -321,9 +322,15 @@ int cskv_program_set_overlap(cskv_program* p, int mode) {
     return CSKV_OK;
 }
 
-static int add_op(cskv_program* p, const Op& o) {
+// every operation keeps the launch shapes the table had when it was added (results never depend
+// on them; a tuner sets them per batch size before each add)
+static int add_op(cskv_program* p, Op o) {
     if (!p || p->ready) return CSKV_EINVAL;
     if (o.n >= (1ull << 31)) return CSKV_EINVAL;
+    o.group = p->table->group;
+    o.prefetch = p->table->prefetch_b2;
+    o.blocks_per_cu = p->table->blocks_per_cu;
+    o.route_group = p->table->route_group;
     p->ops.push_back(o);
     return CSKV_OK;
 }
@@ -341,9 +348,6 @@ int cskv_program_add_find(cskv_program* p, uint64_t n, const uint64_t* d_keys, f
     o.out = d_values_out;
     o.flags = d_found;
     o.scores_out = d_scores_out;
-    o.group = p->table->group;
-    o.prefetch = p->table->prefetch_b2;
-    o.blocks_per_cu = p->table->blocks_per_cu;
     return add_op(p, o);
 }
 
@@ -454,8 +458,8 @@ static int launch_serial(cskv_program* p, hipStream_t s) {
         const Op& o = p->ops[g.first];
         int rc = CSKV_OK;
         if (g.kind == kFind) rc = run_find_run(p, g, s);
-        else if (g.kind == kErase) rc = enqueue_erase(t, o.n, o.keys, o.flags, scratch, sbytes, s);
-        else rc = enqueue_upsert(t, upsert_args(o), scratch, sbytes, s);
+        else if (g.kind == kErase) rc = enqueue_erase(t, o.n, o.keys, o.flags, scratch, sbytes, s, o.group);
+        else rc = enqueue_upsert(t, upsert_args(o), scratch, sbytes, s, o.route_group);
         if (rc != CSKV_OK) return rc;
     }
     return CSKV_OK;
@@ -472,7 +476,7 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
     if (ph.kind == kPhProbe || ph.kind == kPhClear) {
         if (p->scratch_bytes < erase_ws_bytes(o.n)) return CSKV_ENOMEM;
         uint32_t* pos = reinterpret_cast<uint32_t*>(scratch);
-        e = ph.kind == kPhProbe ? launch_erase_probe(t->view, o.n, o.keys, o.flags, pos, t->group, s)
+        e = ph.kind == kPhProbe ? launch_erase_probe(t->view, o.n, o.keys, o.flags, pos, o.group, s)
                                 : launch_erase_clear(t->view, o.n, pos, s);
         return e == hipSuccess ? CSKV_OK : CSKV_EHIP;
     }
@@ -486,11 +490,11 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
         // with route sub-rounds every round routes after the previous one applied: all of it runs
         // in the apply phase (on the writer lane, after the concurrent readers)
         case kPhRoute:
-            if (w.rounds == 1) e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, t->route_group, s);
+            if (w.rounds == 1) e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, o.route_group, s);
             break;
         case kPhApply:
             e = w.rounds == 1 ? launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s)
-                              : launch_upsert_rounds(t->view, w, a.n, a.keys, a.vals, a.scores, a.ev, t->route_group, s);
+                              : launch_upsert_rounds(t->view, w, a.n, a.keys, a.vals, a.scores, a.ev, o.route_group, s);
             break;
         default: e = launch_upsert_finish(w, a.n, a.status, t->view.dim, s); break;
     }
