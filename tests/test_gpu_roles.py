@@ -123,3 +123,37 @@ def test_concurrent_callers_match_sequential_oracle(mode):
     for out, fl in readers:
         assert bool((fl == 1).all()) and torch.equal(bits(out), bits(exp_a)), "a reader saw A change"
     tw.check_table()
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_program_holds_the_table_as_one_call(overlap):
+    """A program with writes is one inserter call under the lock: a find issued on another stream
+    after the launch (or after a graph replay) sees every key the program inserted."""
+    say(f"program under the lock, overlap {overlap}")
+    dim = 8
+    t = cskv.Table(1 << 20, dim, "dual", "custom")
+    t.set_lock_mode("triple_group")
+    n = 1 << 16
+    keys = [gen_keys(95, n, i * n, device="cuda") for i in range(4)]
+    rows = [value_rows(5 + i, torch.arange(n), dim).cuda() for i in range(4)]
+    sc = torch.ones(n, dtype=torch.int64, device="cuda")
+    st = [torch.empty(n, dtype=torch.uint8, device="cuda") for _ in range(4)]
+    pr = cskv.Program(t, overlap=overlap)
+    for i in range(4):
+        pr.add_insert_or_assign(keys[i], rows[i], sc, st[i])
+    pr.finalize()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    pr.launch(s1)
+    with torch.cuda.stream(s2):
+        v, f, _ = t.find(keys[3])
+    torch.cuda.synchronize()
+    assert bool((f == 1).all()) and torch.equal(bits(v), bits(rows[3])), "a reader overtook the program"
+    with torch.cuda.stream(s2):
+        t.erase(torch.cat(keys))
+    pr.capture(s1)
+    pr.replay(s1)
+    with torch.cuda.stream(s2):
+        f2 = t.contains(keys[2])
+    torch.cuda.synchronize()
+    assert bool((f2 == 1).all()), "a reader overtook the replay"
