@@ -65,7 +65,9 @@ def tune_find(table: cskv.Table, queries_by_class: dict, log=None) -> dict:
 
 def tune_route(table: cskv.Table, fresh_by_class: dict, log=None) -> dict:
     """fresh_by_class: class name -> fresh (absent) keys; each trial inserts them and erases them
-    again, so the table ends as it started (no eviction may happen: use a table below full load)."""
+    again, so the table ends as it started unless a trial evicted a resident (possible at high
+    load: one call routes all its keys against the same snapshot and can overfill a bucket);
+    callers that need the table unchanged snapshot its storage around the tuning."""
     out = {}
     dev = table.device
     for cls, k in fresh_by_class.items():

@@ -121,3 +121,76 @@ def test_c2_full_size_properties():
     assert bool((s == clock + 1).all())
     # evicted rows are the rows their keys were inserted with
     assert torch.equal(bits(ev[:m]), bits(value_rows(11, ek[:m], DIM)))
+
+
+def test_c4_full_size_program_properties():
+    """C4 at full size (2^26 slots, dim 32, LRU prefilled to 0.9; 256 batches of 1K-1M keys,
+    70/25/5 find / insert_or_assign / erase, shapes autotuned per size class) as one program:
+    never-inserted keys are never found, every found row is its key's generator row (prefill and
+    upserts share it), fresh keys are admitted, the size follows the statuses, and the program's
+    outputs equal plain calls'."""
+    from paper_2603_17168_amd import autotune as tuner
+    from paper_2603_17168_amd.workload import batch_schedule, program_inputs
+    dev = torch.device("cuda", 0)
+    say("C4 full size: prefill to 0.9")
+    t = cskv.Table(CAP, DIM, "dual", "lru", device=dev)
+    c = 0
+    while t.size() < 0.9 * CAP:
+        k = gen_keys(2, B, c * B, device=dev)
+        t.insert_or_assign(k, value_rows(11, k, DIM), want_status=False)
+        c += 1
+    size0 = t.size()
+    resident = gen_keys(2, size0, 0, device=dev)
+    sched = batch_schedule(21, 256, 1 << 10, 1 << 20)
+    ops = program_inputs(sched, DIM, resident, fresh_stream=22, miss_stream=23, seed=11, device=dev)
+    q = {s: resident[: tuner.CLASS_SIZE[s]] for s in ("small", "medium", "large")}
+    fr = {s: gen_keys(24, tuner.CLASS_SIZE[s], 0, device=dev) for s in ("small", "medium", "large")}
+    tuning = tuner.merge(tuner.tune_find(t, q), tuner.tune_route(t, fr))
+    # the route tuner's 2^20-key trials may evict a resident now and then (snapshot routing
+    # overfills a bucket at this load); conservation counts from the table it leaves
+    size0 = t.size()
+    snap = t.storage.clone()
+    say("plain calls")
+    for d in ops:
+        tuner.apply(t, tuning, d["n"])
+        if d["op"] == "find":
+            t.find(d["keys"], values_out=d["out"], found_out=d["flag"], want_scores=False)
+        elif d["op"] == "upsert":
+            t.insert_or_assign(d["keys"], d["values"], status_out=d["flag"])
+        else:
+            t.erase(d["keys"], erased_out=d["flag"])
+    torch.cuda.synchronize()
+    size_plain = t.size()
+    ref = [(d["flag"].clone(), d["out"].clone() if "out" in d else None) for d in ops]
+    say("the same schedule as one program")
+    t.storage.copy_(snap)
+    pr = cskv.Program(t, overlap=0)
+    for d in ops:
+        tuner.apply(t, tuning, d["n"])
+        if d["op"] == "find":
+            d["out"].zero_()
+            pr.add_find(d["keys"], d["out"], d["flag"])
+        elif d["op"] == "upsert":
+            pr.add_insert_or_assign(d["keys"], d["values"], None, d["flag"])
+        else:
+            pr.add_erase(d["keys"], d["flag"])
+    pr.finalize()
+    pr.launch()
+    torch.cuda.synchronize()
+    assert t.size() == size_plain
+    gained = 0
+    for d, (flag, out) in zip(ops, ref):
+        assert torch.equal(d["flag"], flag), d["op"]
+        if d["op"] == "find":
+            assert torch.equal(bits(d["out"]), bits(out))
+            hit = d["flag"].bool()
+            miss_stream_keys = ~torch.isin(d["keys"], resident)
+            assert not bool((hit & miss_stream_keys).any()), "a never-inserted key was found"
+            assert torch.equal(bits(d["out"][hit]), bits(value_rows(11, d["keys"][hit], DIM))), "a found row differs"
+        elif d["op"] == "upsert":
+            st = d["flag"]
+            assert bool(((st == cskv.ST_INSERTED) | (st == cskv.ST_INSERTED_EVICT)).all()), "a fresh key not admitted"
+            gained += int((st == cskv.ST_INSERTED).sum())
+        else:
+            gained -= torch.unique(d["keys"][d["flag"].bool()]).numel()
+    assert t.size() == size0 + gained, "the size does not follow the statuses"
