@@ -317,8 +317,7 @@ uint32_t cskv_get_route_subrounds(const cskv_table* table);
  * increments may be lost); callers give concurrent updaters disjoint keys.  Workspaces must not
  * be shared by calls that may overlap.  cskv_program_capture takes no role (the replay does).
  * The lock keeps the latest events of the streams it has seen and may query or wait on them in
- * later calls; cskv_set_lock_mode (even to the current mode) waits for all of them and forgets
- * them.  So: call it only while no call is in flight on the table (CSKV_EINVAL otherwise), and
+ * later calls; cskv_set_lock_mode (even to the current mode) forgets all of them.  So: call it only while no call is in flight on the table (CSKV_EINVAL otherwise), and
  * call it after synchronizing, and before destroying, any stream that made calls under a lock.
  * CSKV_EINVAL for another mode.
  */

@@ -205,7 +205,6 @@ struct HipEvents {
     bool record(Event e, Stream s) { return e && hipEventRecord(e, s) == hipSuccess; }
     bool wait(Stream s, Event e) { return hipStreamWaitEvent(s, e, 0) == hipSuccess; }
     bool done(Event e) { return hipEventQuery(e) == hipSuccess; }
-    void sync(Event e) { (void)hipEventSynchronize(e); }
     void destroy(Event e) {
         if (e) (void)hipEventDestroy(e);
     }

@@ -19,11 +19,11 @@
 // still enqueueing its kernels.  The lock keeps events recorded on the callers' streams until
 // later calls no longer need them, and it may query or wait on them then; so before a stream
 // that made calls under the lock is destroyed, the caller synchronizes it and resets the lock
-// (reset() synchronizes and forgets every event it holds).
+// (reset() forgets every event it holds).
 //
 // The lock is a template over its event backend so that the host logic can be tested without a
 // GPU: the backend provides Event, Stream, make(), record(e, s) and wait(s, e) (both returning
-// false on failure), done(e), sync(e) and destroy(e).
+// false on failure), done(e) and destroy(e).
 #pragma once
 
 #include <condition_variable>
@@ -82,8 +82,8 @@ class RoleLock {
         return true;
     }
 
-    // waits for every event the lock holds and forgets them and the groups; false (and nothing
-    // done) while a call is admitted or queued
+    // forgets every event the lock holds and the groups (the caller has synchronized the streams
+    // that recorded them); false (and nothing done) while a call is admitted or queued
     bool reset() {
         std::lock_guard<std::mutex> lk(m_);
         if (!q_.empty() || (cur_ && cur_->pending)) return false;
@@ -203,10 +203,7 @@ class RoleLock {
     void drain_locked() {
         if (prev_) retire(prev_->events);
         if (cur_) retire(cur_->events);
-        for (const Event& e : retired_) {
-            b_.sync(e);
-            b_.destroy(e);
-        }
+        for (const Event& e : retired_) b_.destroy(e);  // a pending event may be destroyed
         for (const Event& e : free_) b_.destroy(e);
         retired_.clear();
         free_.clear();

@@ -46,7 +46,6 @@ struct Recorder {
         return true;
     }
     bool done(Event) { return false; }  // never reused: every event id is unique
-    void sync(Event) {}
     void destroy(Event) {}
 };
 
