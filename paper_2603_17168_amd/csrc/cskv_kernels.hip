@@ -110,7 +110,20 @@ __global__ void __launch_bounds__(256) k_size(TableView t, uint64_t* __restrict_
     const uint64_t nwords = t.nbuckets * (kSlots / 16);
     const uint4* d = reinterpret_cast<const uint4*>(t.dig);
     unsigned int c = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < nwords; i += 4 * stride) {  // four 16-byte loads in flight
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = d[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c += 4 - __popc(match4(w4[q], 0u));
+        }
+    }
+    for (; i < nwords; i += stride) {
         const uint4 v = d[i];
         const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -128,49 +141,87 @@ __global__ void __launch_bounds__(256) k_size(TableView t, uint64_t* __restrict_
 hipError_t launch_size(const TableView& t, uint64_t* d_size, hipStream_t s) {
     hipError_t e = launch_fill_zero(d_size, 8, s);
     if (e != hipSuccess) return e;
-    uint64_t blocks = (t.nbuckets * 8 + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    uint64_t blocks = (t.nbuckets * 8 + 1023) / 1024;  // about four 16-byte words per thread
+    if (blocks > 8192) blocks = 8192;
     k_size<<<(unsigned)blocks, 256, 0, s>>>(t, d_size);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
-// export: one wave per bucket; output positions from one atomic per bucket
-__global__ void __launch_bounds__(64) k_export(TableView t, uint64_t b0, uint64_t b1, uint64_t* __restrict__ keys,
-                                               float* __restrict__ vals, uint64_t* __restrict__ scores,
-                                               uint64_t* __restrict__ slots, uint64_t* __restrict__ count,
-                                               uint64_t min_score) {
+// export: a block of 4 waves takes 16 consecutive buckets (4 per wave).  Each wave forms the
+// occupancy (and predicate) masks of its buckets with ballots; the block adds up the 16 counts
+// and takes its output range with ONE atomic; then every wave writes its buckets' entries at
+// their offsets (output order is unspecified).
+constexpr int kExportWaves = 4;
+constexpr int kExportPerWave = 4;
+constexpr int kExportBuckets = kExportWaves * kExportPerWave;
+
+__global__ void __launch_bounds__(256) k_export(TableView t, uint64_t b0, uint64_t b1, uint64_t* __restrict__ keys,
+                                                float* __restrict__ vals, uint64_t* __restrict__ scores,
+                                                uint64_t* __restrict__ slots, uint64_t* __restrict__ count,
+                                                uint64_t min_score) {
+    __shared__ uint32_t cnt_s[kExportBuckets];
+    __shared__ uint32_t off_s[kExportBuckets];
     __shared__ unsigned long long base_s;
-    __shared__ uint8_t sl[128];
-    const int lane = threadIdx.x;
-    for (uint64_t b = b0 + blockIdx.x; b < b1; b += gridDim.x) {
-        const size_t eb = (size_t)b * kSlots;
-        bool o0 = t.dig[eb + lane] != 0, o1 = t.dig[eb + lane + 64] != 0;
-        if (min_score) {  // export_batch_if: entries whose score is at least min_score
-            o0 = o0 && t.scores[eb + lane] >= min_score;
-            o1 = o1 && t.scores[eb + lane + 64] >= min_score;
-        }
-        const uint64_t bal0 = __ballot(o0), bal1 = __ballot(o1);
-        const int c = __popcll(bal0) + __popcll(bal1);
-        const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-        if (o0) sl[__popcll(bal0 & below)] = (uint8_t)lane;
-        if (o1) sl[__popcll(bal0) + __popcll(bal1 & below)] = (uint8_t)(lane + 64);
-        if (lane == 0) base_s = c ? atomicAdd(reinterpret_cast<unsigned long long*>(count), (unsigned long long)c) : 0ull;
-        __syncthreads();
-        const uint64_t base = base_s;
-        for (int j = lane; j < c; j += 64) {
-            const size_t e = eb + sl[j];
-            keys[base + j] = t.keys[e];
-            if (scores) scores[base + j] = t.scores[e];
-            if (slots) slots[base + j] = e;
-        }
-        if (vals) {
-            const uint32_t chunks = t.dim >> 2;
-            for (uint32_t x = lane; x < (uint32_t)c * chunks; x += 64) {
-                const uint32_t j = x / chunks, cc = x - j * chunks;
-                reinterpret_cast<uint4*>(vals + (base + j) * t.dim)[cc] =
-                    reinterpret_cast<const uint4*>(t.row(eb + sl[j]))[cc];
+    __shared__ uint8_t sl[kExportWaves][128];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (uint64_t tile = b0 + (uint64_t)blockIdx.x * kExportBuckets; tile < b1;
+         tile += (uint64_t)gridDim.x * kExportBuckets) {
+        uint64_t bal0[kExportPerWave], bal1[kExportPerWave];
+#pragma unroll
+        for (int q = 0; q < kExportPerWave; ++q) {
+            const uint64_t b = tile + (uint64_t)wv * kExportPerWave + q;
+            bool o0 = false, o1 = false;
+            if (b < b1) {
+                const size_t eb = (size_t)b * kSlots;
+                o0 = t.dig[eb + lane] != 0;
+                o1 = t.dig[eb + lane + 64] != 0;
+                if (min_score) {  // export_batch_if: entries whose score is at least min_score
+                    o0 = o0 && t.scores[eb + lane] >= min_score;
+                    o1 = o1 && t.scores[eb + lane + 64] >= min_score;
+                }
             }
+            bal0[q] = __ballot(o0);
+            bal1[q] = __ballot(o1);
+            if (lane == 0) cnt_s[wv * kExportPerWave + q] = (uint32_t)(__popcll(bal0[q]) + __popcll(bal1[q]));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int q = 0; q < kExportBuckets; ++q) {
+                off_s[q] = tot;
+                tot += cnt_s[q];
+            }
+            base_s = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(count), (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kExportPerWave; ++q) {
+            const uint64_t b = tile + (uint64_t)wv * kExportPerWave + q;
+            const int c = (int)cnt_s[wv * kExportPerWave + q];
+            if (b >= b1 || c == 0) continue;
+            const size_t eb = (size_t)b * kSlots;
+            const uint64_t base = base_s + off_s[wv * kExportPerWave + q];
+            if ((bal0[q] >> lane) & 1ull) sl[wv][__popcll(bal0[q] & below)] = (uint8_t)lane;
+            if ((bal1[q] >> lane) & 1ull) sl[wv][__popcll(bal0[q]) + __popcll(bal1[q] & below)] = (uint8_t)(lane + 64);
+            __builtin_amdgcn_wave_barrier();  // one wave: its LDS accesses stay in order
+            for (int j = lane; j < c; j += 64) {
+                const size_t e = eb + sl[wv][j];
+                keys[base + j] = t.keys[e];
+                if (scores) scores[base + j] = t.scores[e];
+                if (slots) slots[base + j] = e;
+            }
+            if (vals) {
+                const uint32_t chunks = t.dim >> 2;
+                for (uint32_t x = lane; x < (uint32_t)c * chunks; x += 64) {
+                    const uint32_t j = x / chunks, cc = x - j * chunks;
+                    reinterpret_cast<uint4*>(vals + (base + j) * t.dim)[cc] =
+                        reinterpret_cast<const uint4*>(t.row(eb + sl[wv][j]))[cc];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }
@@ -180,9 +231,9 @@ hipError_t launch_export(const TableView& t, uint64_t b0, uint64_t b1, uint64_t*
                          uint64_t* scores, uint64_t* slots, uint64_t* count, uint64_t min_score, hipStream_t s) {
     hipError_t e = launch_fill_zero(count, 8, s);
     if (e != hipSuccess || b1 <= b0) return e;
-    uint64_t blocks = b1 - b0;
-    if (blocks > 65536) blocks = 65536;
-    k_export<<<(unsigned)blocks, 64, 0, s>>>(t, b0, b1, keys, vals, scores, slots, count, min_score);
+    uint64_t blocks = (b1 - b0 + kExportBuckets - 1) / kExportBuckets;
+    if (blocks > 32768) blocks = 32768;
+    k_export<<<(unsigned)blocks, 256, 0, s>>>(t, b0, b1, keys, vals, scores, slots, count, min_score);
     return hipGetLastError();
 }
 
