@@ -49,13 +49,28 @@ FIND_TRAFFIC = {"source_sha256": "992cc9b7b54e89ce8e20a27c591c7cb6ac6cad36bb58db
                             "0.90": {"hit100": 639.6, "hit50": 504.7}, "1.00": {"hit100": 650.2, "hit50": 516.3}}}
 
 
-def find_source_sha256() -> str:
+# The same two counter runs, summed over the kernels of one insert_or_assign call of 2^20 fresh keys
+# (fill, dedupe, route, apply, finish), bytes per key; recorded for the upsert sources with this
+# SHA-256 (cskv_upsert.hip + cskv_kernels.hip + cskv_device.h + cskv_internal.h).
+UPSERT_TRAFFIC = {"source_sha256": "9aee5ae4ac2ec7142579f50bed81be16cdfef0493c01defba1e370f0d3a7ce08", "dim": 32,
+                  "per_key": {"0.50": 1049.8, "0.75": 1081.7, "0.90": 1097.1, "1.00": 1792.4}}
+
+
+FIND_SOURCES = ("cskv_find.hip", "cskv_device.h", "cskv_internal.h")
+UPSERT_SOURCES = ("cskv_upsert.hip", "cskv_kernels.hip", "cskv_device.h", "cskv_internal.h")
+
+
+def source_sha256(files=FIND_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("cskv_find.hip", "cskv_device.h", "cskv_internal.h"):
+    for f in files:
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_17168_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def find_source_sha256() -> str:
+    return source_sha256(FIND_SOURCES)
 
 
 def find_traffic_per_launch(dim: int, loads, batch: int):
@@ -69,6 +84,20 @@ def find_traffic_per_launch(dim: int, loads, batch: int):
         if rec is None:
             return None
         tot += [rec["hit100"] * batch, rec["hit50"] * batch]
+    return float(np.mean(tot))
+
+
+def upsert_traffic_per_launch(dim: int, loads, batch: int):
+    """Mean measured HBM bytes per insert_or_assign call (all its kernels) over the bench's upsert
+    calls, or None when the counters do not cover them or the upsert sources changed."""
+    if UPSERT_TRAFFIC["source_sha256"] != source_sha256(UPSERT_SOURCES) or UPSERT_TRAFFIC["dim"] != dim:
+        return None
+    tot = []
+    for lam in loads:
+        rec = UPSERT_TRAFFIC["per_key"].get(f"{lam:.2f}")
+        if rec is None:
+            return None
+        tot.append(rec * batch)
     return float(np.mean(tot))
 
 
@@ -846,7 +875,8 @@ def main():
         "api": api,
         "roofline_upsert": {"bound": "hbm", "kernel": "insert_or_assign (every kernel of one call)",
                             "achieved": round(ups_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": round(ups_achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                            "frac": round(ups_achieved / HBM_PEAK_GBS, 4),
+                            "traffic": upsert_traffic_per_launch(dim, [lv.target for lv in levels], batch),
                             "achieved_free_slot_model": round(ups_strict_achieved, 1),
                             "frac_free_slot_model": round(ups_strict_achieved / HBM_PEAK_GBS, 4)},
     }
