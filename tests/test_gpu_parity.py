@@ -183,6 +183,29 @@ def test_value_dims(dim):
     tw.check_table()
 
 
+@pytest.mark.parametrize("dim", [4, 32, 64, 128])
+@pytest.mark.parametrize("n_upd,n_ins", [(1, 1), (2, 2), (6, 9), (10, 30)])
+def test_update_then_evict_in_one_call(dim, n_upd, n_ins):
+    """A full bucket receives, in one call, updates that lower some residents' scores below all
+    others and inserts with higher scores: the victims are the entries just updated, and the
+    evicted rows must be the rows those updates wrote (Alg. 2 runs on the bucket as the updates
+    left it).  Sizes cover the register-held row path (few operations) and the loop path."""
+    say(f"update-then-evict: dim {dim}, {n_upd} updates, {n_ins} inserts")
+    nb = 8
+    tw = Twin(nb * 128, dim, "dual", "custom", seed=dim + n_ins)
+    res = np.array([key_for(3, 3, nb, salt=1 + i) for i in range(128)], dtype=np.uint64)
+    tw.upsert(res, np.arange(10, 138, dtype=np.uint64))
+    tw.check_table()
+    upd = res[[5 + 7 * i for i in range(n_upd)]]
+    ins = np.array([key_for(3, 3, nb, salt=900 + i) for i in range(n_ins)], dtype=np.uint64)
+    keys = np.concatenate([ins[: n_ins // 2], upd, ins[n_ins // 2:]])
+    sc = np.concatenate([np.arange(500, 500 + n_ins // 2), np.arange(1, 1 + n_upd),
+                         np.arange(600, 600 + n_ins - n_ins // 2)]).astype(np.uint64)
+    st = tw.upsert(keys, sc, evict=True)
+    assert (st[n_ins // 2: n_ins // 2 + n_upd] == cskv.ST_UPDATED).all()
+    tw.check_table()
+
+
 def test_api_errors_on_gpu():
     t = cskv.Table(128 * 16, 8, "dual", "custom")
     k = torch.ones(4, dtype=torch.int64, device="cuda")
