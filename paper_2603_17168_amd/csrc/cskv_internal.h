@@ -70,7 +70,7 @@ struct OpEntry {
     uint64_t key;
     uint64_t score;
     uint64_t w;     // dedupe slot << 32 | input position
-    uint64_t slot;  // table slot of an update, kInsertSlot for an insert
+    uint64_t slot;  // bits 0-7: table slot of an update, kInsertSlot for an insert; bits 8-15: the key's digest
 };
 
 struct UpsertWs {

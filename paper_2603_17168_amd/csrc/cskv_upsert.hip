@@ -38,6 +38,7 @@ __device__ __forceinline__ uint64_t overflow_key(uint32_t b, uint32_t r) { retur
 struct Entry {
     uint64_t key, score, w;  // w = dedupe slot << 32 | input position
     uint8_t slot;            // kInsertSlot for an insert
+    uint8_t dg;              // the key's digest, computed once by routing
 };
 
 // the r-th operation routed to bucket b
@@ -49,13 +50,15 @@ __device__ __forceinline__ Entry load_entry(const OpEntry* p) {
     e.score = a.y;
     e.w = c.x;
     e.slot = (uint8_t)c.y;
+    e.dg = (uint8_t)(c.y >> 8);
     return e;
 }
 
-__device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t score, uint64_t w, uint8_t slot) {
+__device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t score, uint64_t w, uint8_t slot,
+                                            uint32_t dg) {
     ulonglong2* q = reinterpret_cast<ulonglong2*>(p);
     q[0] = make_ulonglong2(key, score);
-    q[1] = make_ulonglong2(w, (unsigned long long)slot);
+    q[1] = make_ulonglong2(w, (unsigned long long)slot | ((unsigned long long)(dg & 0xFFu) << 8));
 }
 
 __device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
@@ -238,7 +241,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         }
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         if (r < w.cap) {
-            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot);
+            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot, h.dg);
         } else {
             const uint64_t ok = overflow_key(tgt, r);
             uint64_t q = scratch_hash(ok, w.logP);
@@ -248,32 +251,20 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
                 if (old == 0ull) break;
                 q = (q + 1) & (w.P - 1);
             }
-            store_entry(w.ol + q, k, ns, wv, islot);
+            store_entry(w.ol + q, k, ns, wv, islot, h.dg);
         }
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // fast apply: one 16-lane group per bucket with 1..16 operations
-__device__ __forceinline__ int nth_bit128(uint64_t lo, uint64_t hi, int r) {
-    const int c = __popcll(lo);
-    uint64_t x = lo;
-    int base = 0;
-    if (r >= c) {
-        r -= c;
-        x = hi;
-        base = 64;
-    }
-    for (int q = 0; q < r; ++q) x &= x - 1;
-    return base + __ffsll((unsigned long long)x) - 1;
-}
-
 constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
 
 __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint32_t s_nev[kApplyGroups];
     __shared__ uint32_t s_off[kApplyGroups];
     __shared__ unsigned long long s_base;
+    __shared__ uint8_t s_free[kApplyGroups][GA];  // per group: the free slots taken by the first inserts, by rank
     const int g = threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     const int gshift = (threadIdx.x & 63) & ~(GA - 1);
@@ -320,15 +311,25 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             const uint64_t kx = __shfl(e.key, x, GA);
             rank += (int)(((ins_bits >> x) & 1u) && (sx > e.score || (sx == e.score && kx < e.key)));
         }
-        if (ni > 0 && nfree > 0) {  // the first inserts take the free slots
-            uint64_t elo = 0, ehi = 0;
+        if (ni > 0 && nfree > 0) {  // the first inserts take the free slots, in slot order
+            // free slot of rank r (r < ni <= 16): lane L's free slots follow the free slots of
+            // lanes 0..L-1, found by an exclusive scan of the per-lane counts
+            const int nf = __popc(emask8);
+            int incl = nf;
 #pragma unroll
-            for (int q = 0; q < GA; ++q) {
-                const uint64_t mq = (uint64_t)__shfl((int)emask8, q, GA) & 0xFFull;
-                if (q < 8) elo |= mq << (8 * q);
-                else ehi |= mq << (8 * (q - 8));
+            for (int d = 1; d < GA; d <<= 1) {
+                const int v = __shfl_up(incl, d, GA);
+                if (lane >= d) incl += v;
             }
-            if (is_ins && rank < nfree) new_slot = nth_bit128(elo, ehi, rank);
+            uint32_t f = emask8;
+            for (int r = incl - nf; f && r < ni; ++r) {
+                s_free[g][r] = (uint8_t)(lane * SPL + __ffs(f) - 1);
+                f &= f - 1;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // the group is inside one wave: its LDS accesses stay in order
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (is_ins && rank < nfree) new_slot = s_free[g][rank];
         }
         if (full_after) {  // scores of the bucket, with this call's updates applied
             const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
@@ -424,10 +425,11 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
         if (ns < 0) continue;
         const uint64_t nk = __shfl(e.key, x, GA);
         const uint64_t nsc = __shfl(e.score, x, GA);
+        const int nd = __shfl((int)e.dg, x, GA);
         if ((ns >> 3) == lane) {
             t.keys[eb + ns] = nk;
             t.scores[eb + ns] = nsc;
-            t.dig[eb + ns] = (uint8_t)hash_key(t, nk).dg;
+            t.dig[eb + ns] = (uint8_t)nd;
             if (full_after) {
 #pragma unroll
                 for (int q = 0; q < SPL; ++q)
