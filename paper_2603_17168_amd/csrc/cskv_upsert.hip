@@ -31,6 +31,19 @@ constexpr int GA = 16;            // lanes per bucket in the fast apply kernel
 constexpr int SPL = kSlots / GA;  // slots per lane
 constexpr uint64_t kGold = 0x9E3779B97F4A7C15ull;
 
+// group minimum of (score, key) pairs under (score asc, key asc)
+template <int G>
+__device__ __forceinline__ void gmin_pair(uint64_t& s, uint64_t& k) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const uint64_t os = __shfl_xor(s, o, G), ok = __shfl_xor(k, o, G);
+        if (os < s || (os == s && ok < k)) {
+            s = os;
+            k = ok;
+        }
+    }
+}
+
 __device__ __forceinline__ uint64_t scratch_hash(uint64_t x, int logP) { return (fmix64(x) * kGold) >> (64 - logP); }
 
 __device__ __forceinline__ uint64_t overflow_key(uint32_t b, uint32_t r) { return ((uint64_t)b << 32) + r + 1; }
@@ -260,11 +273,12 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
 // fast apply: one 16-lane group per bucket with 1..16 operations
 constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
 
-__global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint32_t s_nev[kApplyGroups];
     __shared__ uint32_t s_off[kApplyGroups];
     __shared__ unsigned long long s_base;
     __shared__ uint8_t s_free[kApplyGroups][GA];  // per group: the free slots taken by the first inserts, by rank
+    __shared__ uint64_t s_keys[kApplyGroups][kSlots];
     const int g = threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     const int gshift = (threadIdx.x & 63) & ~(GA - 1);
@@ -285,7 +299,10 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
     int new_slot = -1, evi = 0;
     uint64_t vkey = 0, vscore = 0;
     uint32_t taken = 0, upd_bits = 0, ins_bits = 0;
+    // a bucket that ends full: its scores (this call's updates applied) in registers and its keys in
+    // LDS, each lane holding its own 8 slots of both
     uint64_t sc[SPL];
+    uint64_t* kc = s_keys[g] + lane * SPL;
     bool full_after = false;
     uint32_t nev = 0;
 
@@ -331,13 +348,16 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (is_ins && rank < nfree) new_slot = s_free[g][rank];
         }
-        if (full_after) {  // scores of the bucket, with this call's updates applied
+        if (full_after) {  // scores and keys of the bucket, with this call's updates applied
             const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
+            const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(t.keys + eb + lane * SPL);
 #pragma unroll
             for (int q = 0; q < SPL / 2; ++q) {
-                const ulonglong2 v = sp[q];
+                const ulonglong2 v = sp[q], u = kp[q];
                 sc[2 * q] = v.x;
                 sc[2 * q + 1] = v.y;
+                kc[2 * q] = u.x;
+                kc[2 * q + 1] = u.y;
             }
             for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
                 const int x = __ffs(ub) - 1;
@@ -354,26 +374,21 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             const uint32_t rb = (uint32_t)((__ballot(is_ins && rank == nfree + v) >> gshift) & 0xFFFFu);
             const int rl = __ffs(rb) - 1;
             const uint64_t s_in = __shfl(e.score, rl, GA);
-            uint64_t lm = ~0ull;
-#pragma unroll
-            for (int q = 0; q < SPL; ++q)
-                if (!(taken >> q & 1u)) lm = sc[q] < lm ? sc[q] : lm;
-            const uint64_t gm = gmin_u64<GA>(lm);
-            if (!(s_in > gm)) break;  // rejected, and so is every later insert
-            uint64_t lk = ~0ull;
+            // smallest resident by (score, key) among the slots not yet taken
+            uint64_t ls = ~0ull, lk = ~0ull;
             int lslot = -1;
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
-                if (!(taken >> q & 1u) && sc[q] == gm) {  // keys only for slots tied at the minimum
-                    const uint64_t kq = t.keys[eb + lane * SPL + q];
-                    if (kq < lk) {
-                        lk = kq;
-                        lslot = lane * SPL + q;
-                    }
+                if (!(taken >> q & 1u) && (sc[q] < ls || (sc[q] == ls && kc[q] < lk))) {
+                    ls = sc[q];
+                    lk = kc[q];
+                    lslot = lane * SPL + q;
                 }
             }
-            const uint64_t gk = gmin_u64<GA>(lk);
-            const uint32_t ob = (uint32_t)((__ballot(lslot >= 0 && lk == gk) >> gshift) & 0xFFFFu);
+            uint64_t gm = ls, gk = lk;
+            gmin_pair<GA>(gm, gk);
+            if (!(s_in > gm)) break;  // rejected, and so is every later insert
+            const uint32_t ob = (uint32_t)((__ballot(lslot >= 0 && ls == gm && lk == gk) >> gshift) & 0xFFFFu);
             const int ol = __ffs(ob) - 1;
             const int vsl = __shfl(lslot, ol, GA);
             if (lane == ol) taken |= 1u << (vsl & 7);
@@ -433,7 +448,10 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             if (full_after) {
 #pragma unroll
                 for (int q = 0; q < SPL; ++q)
-                    if ((ns & 7) == q) sc[q] = nsc;
+                    if ((ns & 7) == q) {
+                        sc[q] = nsc;
+                        kc[q] = nk;
+                    }
             }
         }
     }
@@ -482,25 +500,20 @@ __global__ void __launch_bounds__(256) k_apply_fast(TableView t, UpsertWs w, con
             for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
         }
     }
-    // cached minimum of a full bucket (exact; every slot is occupied now).  Keys are read back
-    // only for slots tied at the minimum; the owning lane wrote any new key itself.
+    // cached minimum of a full bucket (exact; every slot is occupied now)
     if (full_after) {
-        uint64_t lm = ~0ull;
-#pragma unroll
-        for (int q = 0; q < SPL; ++q) lm = sc[q] < lm ? sc[q] : lm;
-        const uint64_t gm = gmin_u64<GA>(lm);
-        uint64_t lk = ~0ull;
+        uint64_t ls = ~0ull, lk = ~0ull;
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
-            if (sc[q] == gm) {
-                const uint64_t kq = t.keys[eb + lane * SPL + q];
-                lk = kq < lk ? kq : lk;
+            if (sc[q] < ls || (sc[q] == ls && kc[q] < lk)) {
+                ls = sc[q];
+                lk = kc[q];
             }
         }
-        const uint64_t gk = gmin_u64<GA>(lk);
+        gmin_pair<GA>(ls, lk);
         if (lane == 0) {
-            t.bmin[2 * (size_t)b] = gm;
-            t.bmin[2 * (size_t)b + 1] = gk;
+            t.bmin[2 * (size_t)b] = ls;
+            t.bmin[2 * (size_t)b + 1] = lk;
         }
     }
     if (lane == 0) t.cnt[b] = 0;
