@@ -206,6 +206,63 @@ def test_update_then_evict_in_one_call(dim, n_upd, n_ins):
     tw.check_table()
 
 
+@pytest.mark.parametrize("policy", ["custom", "lru", "lfu"])
+def test_full_bucket_call_sequences(policy):
+    """Many small calls on full buckets: a few inserts above and below the residents' scores
+    (evicting or rejected), calls with many inserts, updates beside an insert, assign_scores and
+    erases followed by refills, each followed by whole-table parity with the oracle (the bucket
+    minimum cached for routing must follow every change)."""
+    say(f"full-bucket sequences: {policy}")
+    nb = 4
+    tw = Twin(nb * 128, 8, "dual", policy, seed=7)
+    rng = np.random.default_rng(len(policy))
+    salt = [1]
+    owner = {}  # key -> its bucket (both candidates of every key here are the same bucket)
+
+    def fresh(b, n):
+        k = np.array([key_for(b, b, nb, salt=salt[0] + i) for i in range(n)], dtype=np.uint64)
+        salt[0] += n
+        owner.update((int(x), b) for x in k)
+        return k
+
+    def residents_of(b):
+        return np.array([x for x in tw.ora.export()[0] if owner.get(int(x)) == b], dtype=np.uint64)
+
+    def scores(n, lo, hi):
+        if policy == "custom":
+            return rng.integers(lo, hi, n).astype(np.uint64)
+        if policy == "lfu":
+            return rng.integers(1, 4, n).astype(np.uint64)
+        return None
+
+    for b in (1, 2):
+        tw.upsert(fresh(b, 128), scores(128, 100, 1000))
+    tw.check_table()
+    for step in range(60):
+        b = 1 + step % 2
+        r = rng.random()
+        if r < 0.55:  # a few inserts
+            k = fresh(b, int(rng.integers(1, 7)))
+            tw.upsert(k, scores(k.size, 0, 1200), evict=bool(rng.random() < 0.5))
+        elif r < 0.65:  # many inserts
+            k = fresh(b, int(rng.integers(7, 16)))
+            tw.upsert(k, scores(k.size, 0, 1200), evict=True)
+        elif r < 0.75:  # updates of residents (plus an insert) in one call
+            mine = residents_of(b)
+            k = np.concatenate([rng.choice(mine, 2, replace=False), fresh(b, 1)])
+            tw.upsert(k, scores(k.size, 0, 1200))
+        elif r < 0.85 and policy != "lru":  # assign_scores: scores change in place
+            mine = residents_of(b)
+            k = rng.choice(mine, 3, replace=False)
+            tw.assign(k, scores(k.size, 0, 1200), with_values=False)
+        else:  # erase, then refill to full
+            mine = residents_of(b)
+            k = rng.choice(mine, int(rng.integers(1, 4)), replace=False)
+            tw.erase(k)
+            tw.upsert(fresh(b, k.size), scores(k.size, 500, 1500))
+        tw.check_table()
+
+
 def test_api_errors_on_gpu():
     t = cskv.Table(128 * 16, 8, "dual", "custom")
     k = torch.ones(4, dtype=torch.int64, device="cuda")
