@@ -44,16 +44,16 @@ def log(*a):
 # `bench.py --counter-probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter read
 # for a 1 GiB device copy in the same run; recorded for the find source with this SHA-256
 # (cskv_find.hip + cskv_device.h + cskv_internal.h) and reported only while that source is unchanged.
-FIND_TRAFFIC = {"source_sha256": "992cc9b7b54e89ce8e20a27c591c7cb6ac6cad36bb58db8cb048ce0d9ce80826", "dim": 32,
-                "per_key": {"0.50": {"hit100": 602.7, "hit50": 460.8}, "0.75": {"hit100": 625.2, "hit50": 487.8},
-                            "0.90": {"hit100": 639.6, "hit50": 504.7}, "1.00": {"hit100": 650.2, "hit50": 516.3}}}
+FIND_TRAFFIC = {"source_sha256": "4da5e9f1c3490ba1cd4021ba71cd99713836aa22060174d14c10174228c032cb", "dim": 32,
+                "per_key": {"0.50": {"hit100": 602.5, "hit50": 460.8}, "0.75": {"hit100": 625.3, "hit50": 487.8},
+                            "0.90": {"hit100": 639.6, "hit50": 504.9}, "1.00": {"hit100": 650.3, "hit50": 516.2}}}
 
 
 # The same two counter runs, summed over the kernels of one insert_or_assign call of 2^20 fresh keys
 # (fill, dedupe, route, apply, finish), bytes per key; recorded for the upsert sources with this
 # SHA-256 (cskv_upsert.hip + cskv_kernels.hip + cskv_device.h + cskv_internal.h).
-UPSERT_TRAFFIC = {"source_sha256": "9aee5ae4ac2ec7142579f50bed81be16cdfef0493c01defba1e370f0d3a7ce08", "dim": 32,
-                  "per_key": {"0.50": 1049.8, "0.75": 1081.7, "0.90": 1097.1, "1.00": 1792.4}}
+UPSERT_TRAFFIC = {"source_sha256": "9960762fc9a814e33f47d83ee9fc940b83f0c335d3886376ef199c4b3dbaf92d", "dim": 32,
+                  "per_key": {"0.50": 1049.8, "0.75": 1081.7, "0.90": 1097.2, "1.00": 2108.4}}
 
 
 FIND_SOURCES = ("cskv_find.hip", "cskv_device.h", "cskv_internal.h")
