@@ -374,16 +374,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             const uint32_t rb = (uint32_t)((__ballot(is_ins && rank == nfree + v) >> gshift) & 0xFFFFu);
             const int rl = __ffs(rb) - 1;
             const uint64_t s_in = __shfl(e.score, rl, GA);
-            // smallest resident by (score, key) among the slots not yet taken
+            // smallest resident by (score, key) among the slots not yet taken; the lane's keys are
+            // read from LDS two at a time and compared without branches
             uint64_t ls = ~0ull, lk = ~0ull;
             int lslot = -1;
+            const ulonglong2* kp2 = reinterpret_cast<const ulonglong2*>(kc);
 #pragma unroll
-            for (int q = 0; q < SPL; ++q) {
-                if (!(taken >> q & 1u) && (sc[q] < ls || (sc[q] == ls && kc[q] < lk))) {
-                    ls = sc[q];
-                    lk = kc[q];
-                    lslot = lane * SPL + q;
+            for (int q2 = 0; q2 < SPL / 2; ++q2) {
+                const ulonglong2 kk = kp2[q2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int q = 2 * q2 + h;
+                    const uint64_t kq = h ? kk.y : kk.x;
+                    const bool better = (((taken >> q) & 1u) == 0u) & ((sc[q] < ls) | ((sc[q] == ls) & (kq < lk)));
+                    ls = better ? sc[q] : ls;
+                    lk = better ? kq : lk;
+                    lslot = better ? lane * SPL + q : lslot;
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             uint64_t gm = ls, gk = lk;
             gmin_pair<GA>(gm, gk);
@@ -503,12 +511,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     // cached minimum of a full bucket (exact; every slot is occupied now)
     if (full_after) {
         uint64_t ls = ~0ull, lk = ~0ull;
+        const ulonglong2* kp2 = reinterpret_cast<const ulonglong2*>(kc);
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            if (sc[q] < ls || (sc[q] == ls && kc[q] < lk)) {
-                ls = sc[q];
-                lk = kc[q];
+        for (int q2 = 0; q2 < SPL / 2; ++q2) {
+            const ulonglong2 kk = kp2[q2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 2 * q2 + h;
+                const uint64_t kq = h ? kk.y : kk.x;
+                const bool better = (sc[q] < ls) | ((sc[q] == ls) & (kq < lk));
+                ls = better ? sc[q] : ls;
+                lk = better ? kq : lk;
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
         gmin_pair<GA>(ls, lk);
         if (lane == 0) {
