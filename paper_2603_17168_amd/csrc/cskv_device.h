@@ -42,28 +42,49 @@ __device__ __forceinline__ int glane() {
     return threadIdx.x & (G - 1);
 }
 
+// Exchange inside aligned groups of up to 16 lanes by DPP lane moves (no LDS traffic): step 0
+// swaps lanes i and i^1, step 1 swaps i and i^2 (quad permutes), step 2 mirrors each 8-lane half
+// of a 16-lane row, step 3 mirrors the row.  In a reduction, after steps 0..s-1 every lane holds
+// its block's partial result, so step s pairs each block with the other half of the next larger
+// block and the result reaches every lane.  Groups wider than 16 lanes finish with shuffles.
+template <int S>
+__device__ __forceinline__ int dpp_xchg(int v) {
+    constexpr int ctrl = S == 0 ? 0xB1 : S == 1 ? 0x4E : S == 2 ? 0x141 : 0x140;
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t dpp_xchg(uint64_t v) {
+    const uint32_t lo = (uint32_t)dpp_xchg<S>((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)dpp_xchg<S>((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int G, typename T, typename Op>
+__device__ __forceinline__ T group_reduce(T v, Op op) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group size");
+    if constexpr (G >= 2) v = op(v, dpp_xchg<0>(v));
+    if constexpr (G >= 4) v = op(v, dpp_xchg<1>(v));
+    if constexpr (G >= 8) v = op(v, dpp_xchg<2>(v));
+    if constexpr (G >= 16) v = op(v, dpp_xchg<3>(v));
+    if constexpr (G >= 32) v = op(v, (T)__shfl_xor(v, 16, G));
+    if constexpr (G >= 64) v = op(v, (T)__shfl_xor(v, 32, G));
+    return v;
+}
+
 template <int G>
 __device__ __forceinline__ int gmax_i(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, G));
-    return v;
+    return group_reduce<G>(v, [](int a, int b) { return max(a, b); });
 }
 
 template <int G>
 __device__ __forceinline__ int gsum_i(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
+    return group_reduce<G>(v, [](int a, int b) { return a + b; });
 }
 
 template <int G>
 __device__ __forceinline__ uint64_t gmin_u64(uint64_t v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        uint64_t x = __shfl_xor(v, o, G);
-        v = x < v ? x : v;
-    }
-    return v;
+    return group_reduce<G>(v, [](uint64_t a, uint64_t b) { return b < a ? b : a; });
 }
 
 // byte-equality of a 32-bit word with a broadcast byte: 4 result bits (byte q -> bit q)

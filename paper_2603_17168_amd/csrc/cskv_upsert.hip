@@ -31,17 +31,23 @@ constexpr int GA = 16;            // lanes per bucket in the fast apply kernel
 constexpr int SPL = kSlots / GA;  // slots per lane
 constexpr uint64_t kGold = 0x9E3779B97F4A7C15ull;
 
-// group minimum of (score, key) pairs under (score asc, key asc)
+// group minimum of (score, key) pairs under (score asc, key asc), by the DPP exchange steps of
+// the group reductions (G <= 16)
+template <int S>
+__device__ __forceinline__ void min_pair_step(uint64_t& s, uint64_t& k) {
+    const uint64_t os = dpp_xchg<S>(s), ok = dpp_xchg<S>(k);
+    const bool take = os < s || (os == s && ok < k);
+    s = take ? os : s;
+    k = take ? ok : k;
+}
+
 template <int G>
 __device__ __forceinline__ void gmin_pair(uint64_t& s, uint64_t& k) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        const uint64_t os = __shfl_xor(s, o, G), ok = __shfl_xor(k, o, G);
-        if (os < s || (os == s && ok < k)) {
-            s = os;
-            k = ok;
-        }
-    }
+    static_assert(G == 16, "16-lane groups");
+    min_pair_step<0>(s, k);
+    min_pair_step<1>(s, k);
+    min_pair_step<2>(s, k);
+    min_pair_step<3>(s, k);
 }
 
 __device__ __forceinline__ uint64_t scratch_hash(uint64_t x, int logP) { return (fmix64(x) * kGold) >> (64 - logP); }
