@@ -745,6 +745,9 @@ def main():
     if not args.no_api:
         ptrs = torch.empty(batch, dtype=torch.int64, device=dev)
         fo_rows = torch.empty((batch, dim), dtype=torch.float32, device=dev)
+        ev_out = (torch.empty(batch, dtype=torch.uint8, device=dev), torch.empty(batch, dtype=torch.int64, device=dev),
+                  torch.empty((batch, dim), dtype=torch.float32, device=dev),
+                  torch.empty(batch, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
 
         def timed(fn, reps=3):
             ms = []
@@ -789,6 +792,19 @@ def main():
             r["insert_or_assign_subrounds4_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
             if lv.target < 1.0:
                 t.erase(fk4, erased_out=erased)
+            # insert_and_evict of fresh keys (every insert evicts at load 1), beside the plain
+            # insert_or_assign of the same shape (erased again below load 1)
+            fk5 = gen_keys(870 + li, batch, 0, device=dev)
+            t.workspace(cskv.OP_INSERT_AND_EVICT, batch)  # grown before the timed call
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t.insert_and_evict(fk5, rows, out=ev_out)
+            e1.record()
+            torch.cuda.synchronize()
+            r["insert_and_evict_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
+            if lv.target < 1.0:
+                t.erase(fk5, erased_out=erased)
             # find_or_insert of half resident, half fresh keys; the fresh ones are erased again
             fk = torch.cat([q100[li][: batch // 2], gen_keys(850 + li, batch - batch // 2, 0, device=dev)])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
