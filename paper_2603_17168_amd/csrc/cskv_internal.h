@@ -94,6 +94,9 @@ struct UpsertWs {
     float* out;      // find_or_insert: rows returned per occurrence (resident rows are kept); else null
     int rounds;      // route sub-rounds of the call (1: the whole batch routes at once)
     int round;       // the sub-round a route / apply launch serves
+    int fused = 0;   // routing claimed the dedupe entries itself (first occurrences route; the
+                     // apply takes the last occurrence's position and score from the set)
+    const uint64_t* in_scores = nullptr;  // the call's scores (CUSTOM scores or LFU increments), for that fix-up
 };
 
 // one batch of a merged run of finds (reader group): keys [begin, begin + n) of the run

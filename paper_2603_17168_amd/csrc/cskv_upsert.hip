@@ -17,6 +17,9 @@
 //   slow     one wave per bucket that received more than 16 operations: same rules, with the
 //            best 128 inserts kept in LDS
 //   finish   per-occurrence status
+// A plain call of one route round fuses dedupe and route (the first occurrence of a key claims
+// its set entry and routes it; k_fixup then hands each operation its last occurrence's position
+// and score when some key repeated); programs and route sub-rounds keep the separate passes.
 // Every write to a table slot's key/score/digest is made by the lane that owns the slot, and
 // every 16-byte chunk c of a row by lane c mod (lanes), so writes that must follow one another
 // (an update, then the eviction of the same entry) are ordered by program order.
@@ -86,6 +89,41 @@ __device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint
     uint64_t q = scratch_hash(ok, w.logP);
     for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
     return load_entry(w.ol + q);
+}
+
+// where the r-th operation routed to bucket b is stored
+__device__ __forceinline__ OpEntry* entry_ptr(const UpsertWs& w, uint32_t b, uint32_t r) {
+    if (r < w.cap) return w.il + (size_t)b * w.cap + r;
+    const uint64_t ok = overflow_key(b, r);
+    uint64_t q = scratch_hash(ok, w.logP);
+    for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
+    return w.ol + q;
+}
+
+// After a fused routing pass in a call that repeated a key (else it returns at once): every
+// operation takes its key's last occurrence's position and score (CUSTOM: that occurrence's
+// score; LFU: the saturated sum of the increments, added to the resident score for an update).
+// One thread per bucket.
+__global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w) {
+    if (w.ctr[kCtrDup] == 0) return;
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= t.nbuckets) return;
+    const uint32_t m = t.cnt[b];
+    for (uint32_t r = 0; r < m; ++r) {
+        OpEntry* op = entry_ptr(w, (uint32_t)b, r);
+        Entry e = load_entry(op);
+        const uint32_t p = (uint32_t)(e.w >> 32);
+        const DedupeEntry de = w.dd[p];
+        const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
+        uint64_t score = e.score;
+        if (t.policy == 0) {
+            score = w.in_scores[last];
+        } else if (t.policy == 2) {
+            const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
+            score = e.slot == kInsertSlot ? inc : sat_add(t.scores[b * kSlots + e.slot], inc);
+        }
+        store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -185,18 +223,29 @@ __global__ void __launch_bounds__(256) k_rank_write(UpsertWs w, uint64_t n) {
 }
 
 // ------------------------------------------------------------------------------------------
-template <int G>
+// FUSED: the routing kernel also claims the dedupe entries (one CAS per occurrence, by the
+// group's lane 0, issued after the digest loads); the claiming occurrence routes the key with its
+// own position and score (routing depends only on the key and the table before the call), later
+// occurrences only record themselves, and the apply replaces position and score by the last
+// occurrence's when the call repeated a key.  Otherwise the dedupe pass ran before, and only each
+// key's last occurrence routes.
+template <int G, bool FUSED>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                               const uint64_t* __restrict__ scores) {
+                                               const uint64_t* __restrict__ scores, uint64_t* ev_count) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    if (i >= n) return;
     const int lane = glane<G>();
-    const uint32_t p = w.slot_of[i];
-    if (p == kNoSlot) return;
-    const bool dups = w.ctr[kCtrDup] != 0;  // else every occurrence is its key's last and only one
-    if (dups) {
-        const DedupeEntry de = w.dd[p];
-        if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+    if (FUSED && i == 0 && lane == 0 && ev_count) *ev_count = 0;
+    if (i >= n) return;
+    uint32_t p;
+    bool dups = false;
+    if constexpr (!FUSED) {
+        p = w.slot_of[i];
+        if (p == kNoSlot) return;
+        dups = w.ctr[kCtrDup] != 0;  // else every occurrence is its key's last and only one
+        if (dups) {
+            const DedupeEntry de = w.dd[p];
+            if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
+        }
     }
     if (w.rounds > 1) {  // only the keys of this sub-round's chunk
         const uint64_t nd = w.ctr[kCtrDistinct];
@@ -207,8 +256,44 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     const KeyHash h = hash_key(t, k);
     const bool two = h.b2 != h.b1;
     LineSeg<G> s1, s2;
+    if (FUSED && reserved_key(k)) {
+        if (lane == 0) w.slot_of[i] = kNoSlot;
+        return;
+    }
     s1.load(t.dig + (size_t)h.b1 * kSlots, lane);
     if (two) s2.load(t.dig + (size_t)h.b2 * kSlots, lane);  // an insert needs both occupancies
+    if constexpr (FUSED) {
+        int claimed = 0;
+        uint32_t q = 0;
+        if (lane == 0) {
+            const uint64_t mask = w.P - 1;
+            uint64_t x = scratch_hash(k, w.logP);
+            for (uint64_t probes = 0; probes < w.P; ++probes) {
+                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[x].key), 0ull,
+                                                         (unsigned long long)k);
+                if (old == 0ull) {
+                    w.dd[x].claim = (uint32_t)(i + 1);
+                    claimed = 1;
+                    break;
+                }
+                if (old == k) {
+                    atomicMax(&w.dd[x].last, (uint32_t)(i + 1));
+                    w.ctr[kCtrDup] = 1;
+                    break;
+                }
+                x = (x + 1) & mask;
+            }
+            q = (uint32_t)x;
+            w.slot_of[i] = q;
+            if (t.policy == 2) {  // LFU: saturating sum of the increments
+                const uint64_t inc = scores ? scores[i] : 1ull;
+                const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + x), (unsigned long long)inc);
+                if (old + inc < old) atomicOr(w.sat + x, 1u);
+            }
+        }
+        p = (uint32_t)__shfl((int)q, 0, G);
+        if (!__shfl(claimed, 0, G)) return;
+    }
     int slot = verify<G>(t, h.b1, s1.match(h.dg), k, lane);
     uint32_t tgt = h.b1;
     if (slot < 0 && two) {
@@ -216,7 +301,7 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         tgt = h.b2;
     }
     uint64_t inc = 0;
-    if (t.policy == 2) inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);
+    if (t.policy == 2) inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);  // FUSED: provisional
     uint64_t ns;
     uint8_t islot;
     if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
@@ -804,8 +889,11 @@ __global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t*
 
 template <int G>
 static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
-                         hipStream_t s) {
-    k_route<G><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores);
+                         hipStream_t s, uint64_t* ev_count = nullptr) {
+    if (w.fused)
+        k_route<G, true><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, ev_count);
+    else
+        k_route<G, false><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, nullptr);
 }
 
 hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
@@ -870,12 +958,23 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
                          const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
                          hipStream_t s) {
     hipError_t e;
-    if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
     if (w.rounds > 1) {
+        if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
         if ((e = launch_upsert_rounds(t, w, n, keys, vals, scores, ev, group, s)) != hipSuccess) return e;
-    } else {
-        if ((e = launch_upsert_route(t, w, n, keys, scores, group, s)) != hipSuccess) return e;
-        if ((e = launch_upsert_apply(t, w, n, vals, ev, s)) != hipSuccess) return e;
+    } else {  // one pass claims the dedupe entries and routes
+        if (n == 0) return hipSuccess;
+        if ((e = launch_fill_zero(w.dd, zero_bytes, s)) != hipSuccess) return e;
+        UpsertWs wf = w;
+        wf.fused = 1;
+        wf.in_scores = scores;
+        switch (group) {
+            case 4: launch_route<4>(t, wf, n, keys, scores, s, ev.count); break;
+            case 16: launch_route<16>(t, wf, n, keys, scores, s, ev.count); break;
+            default: launch_route<8>(t, wf, n, keys, scores, s, ev.count); break;
+        }
+        k_fixup<<<(unsigned)((t.nbuckets + 255) / 256), 256, 0, s>>>(t, wf);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_upsert_apply(t, wf, n, vals, ev, s)) != hipSuccess) return e;
     }
     return launch_upsert_finish(w, n, status, t.dim, s);
 }
