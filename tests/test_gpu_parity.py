@@ -263,6 +263,35 @@ def test_full_bucket_call_sequences(policy):
         tw.check_table()
 
 
+@pytest.mark.parametrize("policy", ["custom", "lru", "lfu"])
+@pytest.mark.parametrize("evict", [False, True])
+def test_repeated_keys_take_last_occurrence(policy, evict):
+    """Keys repeated three times in one call, far apart, with different values and scores: some
+    resident (updates), some fresh (inserts). The call must act as the key's last occurrence
+    (its row; CUSTOM: its score; LFU: the sum of the increments, added to a resident's score),
+    every occurrence reporting that operation's status; whole-table parity after each call."""
+    say(f"repeated keys: {policy}, evict {evict}")
+    nb = 32  # 4096 slots: the later calls also evict
+    tw = Twin(nb * 128, 16, "dual", policy, seed=3)
+    rng = np.random.default_rng(5)
+    resident = np_keys(70, 3000)
+    tw.upsert(resident, rng.integers(1, 50, resident.size).astype(np.uint64) if policy != "lru" else None)
+    tw.check_table()
+    for step in range(4):
+        fresh = np_keys(71, 400, step * 400)
+        again = rng.choice(resident, 300, replace=False)
+        base = np.concatenate([fresh, again])
+        keys = np.concatenate([base, rng.permutation(base), rng.permutation(base)])
+        if policy == "custom":
+            sc = rng.integers(0, 100, keys.size).astype(np.uint64)
+        elif policy == "lfu":
+            sc = rng.integers(1, 5, keys.size).astype(np.uint64)
+        else:
+            sc = None
+        tw.upsert(keys, sc, evict=evict)
+        tw.check_table()
+
+
 def test_api_errors_on_gpu():
     t = cskv.Table(128 * 16, 8, "dual", "custom")
     k = torch.ones(4, dtype=torch.int64, device="cuda")
