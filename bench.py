@@ -45,14 +45,14 @@ def log(*a):
 # for a 1 GiB device copy in the same run; recorded for the find source with this SHA-256
 # (cskv_find.hip + cskv_device.h + cskv_internal.h) and reported only while that source is unchanged.
 FIND_TRAFFIC = {"source_sha256": "f6d274a46dd342e14f4ea676e5db3e8a2807a7b2674dad971dac47a3a85ada0d", "dim": 32,
-                "per_key": {"0.50": {"hit100": 602.7, "hit50": 460.8}, "0.75": {"hit100": 625.4, "hit50": 487.9},
-                            "0.90": {"hit100": 639.4, "hit50": 504.7}, "1.00": {"hit100": 650.3, "hit50": 516.3}}}
+                "per_key": {"0.50": {"hit100": 602.8, "hit50": 460.8}, "0.75": {"hit100": 625.3, "hit50": 487.8},
+                            "0.90": {"hit100": 639.5, "hit50": 504.9}, "1.00": {"hit100": 649.9, "hit50": 516.4}}}
 
 
 # The same two counter runs, summed over the kernels of one insert_or_assign call of 2^20 fresh keys
 # (fill, dedupe, route, apply, finish), bytes per key; recorded for the upsert sources with this
 # SHA-256 (cskv_upsert.hip + cskv_kernels.hip + cskv_device.h + cskv_internal.h).
-UPSERT_TRAFFIC = {"source_sha256": "684254b97d67612709ec3a364f59354e5c19937aedae4160add64f18c713997c", "dim": 32,
+UPSERT_TRAFFIC = {"source_sha256": "42f29a99030657bd46db5ac925c56dff9a8efdb915923cc13583d9a4fc553c4a", "dim": 32,
                   "per_key": {"0.50": 1038.6, "0.75": 1070.4, "0.90": 1085.8, "1.00": 2102.1}}
 
 

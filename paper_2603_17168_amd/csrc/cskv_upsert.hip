@@ -103,26 +103,28 @@ __device__ __forceinline__ OpEntry* entry_ptr(const UpsertWs& w, uint32_t b, uin
 // After a fused routing pass in a call that repeated a key (else it returns at once): every
 // operation takes its key's last occurrence's position and score (CUSTOM: that occurrence's
 // score; LFU: the saturated sum of the increments, added to the resident score for an update).
-// One thread per bucket.
+// A grid-stride loop over the buckets on a small grid, so that the common case (no repeats)
+// costs little more than one flag read.
 __global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w) {
     if (w.ctr[kCtrDup] == 0) return;
-    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= t.nbuckets) return;
-    const uint32_t m = t.cnt[b];
-    for (uint32_t r = 0; r < m; ++r) {
-        OpEntry* op = entry_ptr(w, (uint32_t)b, r);
-        Entry e = load_entry(op);
-        const uint32_t p = (uint32_t)(e.w >> 32);
-        const DedupeEntry de = w.dd[p];
-        const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
-        uint64_t score = e.score;
-        if (t.policy == 0) {
-            score = w.in_scores[last];
-        } else if (t.policy == 2) {
-            const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
-            score = e.slot == kInsertSlot ? inc : sat_add(t.scores[b * kSlots + e.slot], inc);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < t.nbuckets; b += stride) {
+        const uint32_t m = t.cnt[b];
+        for (uint32_t r = 0; r < m; ++r) {
+            OpEntry* op = entry_ptr(w, (uint32_t)b, r);
+            Entry e = load_entry(op);
+            const uint32_t p = (uint32_t)(e.w >> 32);
+            const DedupeEntry de = w.dd[p];
+            const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
+            uint64_t score = e.score;
+            if (t.policy == 0) {
+                score = w.in_scores[last];
+            } else if (t.policy == 2) {
+                const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
+                score = e.slot == kInsertSlot ? inc : sat_add(t.scores[b * kSlots + e.slot], inc);
+            }
+            store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg);
         }
-        store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg);
     }
 }
 
@@ -972,7 +974,8 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
             case 16: launch_route<16>(t, wf, n, keys, scores, s, ev.count); break;
             default: launch_route<8>(t, wf, n, keys, scores, s, ev.count); break;
         }
-        k_fixup<<<(unsigned)((t.nbuckets + 255) / 256), 256, 0, s>>>(t, wf);
+        const uint64_t fb = (t.nbuckets + 255) / 256;
+        k_fixup<<<(unsigned)(fb < 256 ? fb : 256), 256, 0, s>>>(t, wf);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_upsert_apply(t, wf, n, vals, ev, s)) != hipSuccess) return e;
     }
