@@ -19,7 +19,8 @@
 //   finish   per-occurrence status
 // A plain call of one route round fuses dedupe and route (the first occurrence of a key claims
 // its set entry and routes it; k_fixup then hands each operation its last occurrence's position
-// and score when some key repeated); programs and route sub-rounds keep the separate passes.
+// and score when some key repeated); phased programs and route sub-rounds keep the separate
+// passes.
 // Every write to a table slot's key/score/digest is made by the lane that owns the slot, and
 // every 16-byte chunk c of a row by lane c mod (lanes), so writes that must follow one another
 // (an update, then the eviction of the same entry) are ordered by program order.
