@@ -37,6 +37,8 @@ def _load():
     lib.ora_create.restype = P
     lib.ora_create.argtypes = [U64, ctypes.c_uint32, ctypes.c_int, ctypes.c_int]
     lib.ora_destroy.argtypes = [P]
+    lib.ora_clone.restype = P
+    lib.ora_clone.argtypes = [P]
     lib.ora_clock.restype = U64
     lib.ora_clock.argtypes = [P]
     lib.ora_size.restype = U64
@@ -92,6 +94,16 @@ class Oracle:
         if not self.h:
             raise ValueError("invalid oracle table arguments")
         self.B, self.S, self.mode, self.policy = n_buckets, bucket_size, mode, policy
+
+    def clone(self) -> "Oracle":
+        """An independent copy of the whole table state."""
+        c = Oracle.__new__(Oracle)
+        c.lib = self.lib
+        c.h = self.lib.ora_clone(self.h)
+        if not c.h:
+            raise MemoryError("oracle clone failed")
+        c.B, c.S, c.mode, c.policy = self.B, self.S, self.mode, self.policy
+        return c
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -141,6 +141,18 @@ ora_table* ora_create(uint64_t B, uint32_t S, int mode, int policy) {
     return t;
 }
 
+/* an independent copy of a table's whole state (entries, counts, clock, settings) */
+ora_table* ora_clone(const ora_table* src) {
+    if (!src) return NULL;
+    ora_table* t = ora_create(src->B, src->S, src->mode, src->policy);
+    if (!t) return NULL;
+    memcpy(t->e, src->e, (size_t)src->B * src->S * sizeof(ora_entry));
+    memcpy(t->cnt, src->cnt, (size_t)src->B * sizeof(uint32_t));
+    t->clock = src->clock;
+    t->subrounds = src->subrounds;
+    return t;
+}
+
 void ora_destroy(ora_table* t) {
     if (!t) return;
     free(t->e);
