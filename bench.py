@@ -33,7 +33,8 @@ from paper_2603_17168_amd.workload import (Zipf, batch_schedule, keys as gen_key
 
 METRIC = "find & upsert B-KV/s at load 0.5–1.0, % of HBM peak; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
-K_B, F_B, L_B, S_B = 8, 1, 128, 64  # input key, found flag, digest line, DRAM access granule
+K_B, F_B, L_B = 8, 1, 128  # input key, found flag, digest line
+S_B = 64  # DRAM access granule of a random read; replaced by the value calibrated on the device in main()
 
 
 def log(*a):
@@ -141,16 +142,17 @@ def share_in_b2(keys: torch.Tensor, slots: torch.Tensor, nbuckets: int) -> float
     return float(((slots // 128) != bucket_b1(keys, nbuckets)).double().mean().item()) if keys.numel() else 0.0
 
 
-def copy_peak_gbs(dev, gib: int = 4, reps: int = 5) -> float:
-    """Device-to-device copy bandwidth (bytes read + written per second), median of `reps`."""
-    a = torch.empty(gib << 28, dtype=torch.float32, device=dev).fill_(1.0)
+def copy_peak_gbs(dev, gib: int = 2, reps: int = 5) -> float:
+    """Copy bandwidth (bytes read + written per second) of the library's 16-byte-per-lane copy
+    kernel (cskv_probe_copy) over `gib` GiB, median of `reps`."""
+    a = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
+    cskv.probe_copy(a, b)
     ms = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        b.copy_(a)
+        cskv.probe_copy(a, b)
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
@@ -159,12 +161,57 @@ def copy_peak_gbs(dev, gib: int = 4, reps: int = 5) -> float:
     return 2.0 * (gib << 30) / (float(np.median(ms)) / 1e3) / 1e9
 
 
+def find_kernel_name(tu: dict) -> str:
+    """The find kernel a launch shape runs (two keys per lane group, or one)."""
+    g, pre = tu.get("find_group", 8), "true" if tu.get("find_prefetch_b2", 0) else "false"
+    return f"k_find_x2<{g}, {pre}>" if tu.get("find_pairs", 0) else f"k_find<{g}, {pre}>"
+
+
+def find_kernel_names(tunings, levels) -> str:
+    names = [find_kernel_name(tu) for tu in tunings]
+    if len(set(names)) == 1:
+        return f"{names[0]} (the autotuned shape at every load)"
+    return "; ".join(f"{lv.target:.2f}: {n}" for lv, n in zip(levels, names))
+
+
+def calibrate_granule(dev, gib: int = 4, n: int = 1 << 24, reps: int = 5) -> dict:
+    """Random-gather microbenchmark (cskv_probe_gather) over a `gib` GiB array, far beyond the
+    last-level cache: the access rate of 8-byte reads and of 128-byte reads.  A random read costs
+    whole DRAM access granules, so rate_8 / rate_128 = 128 / s, and s = 128 * rate_128 / rate_8
+    is the granule a random 8-byte read really moves."""
+    src = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+    out = torch.empty(n * 128, dtype=torch.uint8, device=dev)
+    rate = {}
+    for width in (8, 32, 64, 128):
+        ms = []
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cskv.probe_gather(src, width, n, 1000 + r, out)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        rate[width] = n / (float(np.median(ms)) / 1e3)
+    del src, out
+    torch.cuda.empty_cache()
+    s = 128.0 * rate[128] / rate[8]
+    model = min((32, 64, 128), key=lambda g: abs(np.log2(s / g)))
+    return {"granule_bytes": round(s, 1), "granule_model_bytes": model,
+            "gather_rate_g_per_s": {str(w): round(r / 1e9, 2) for w, r in rate.items()},
+            "gather128_gbs": round(rate[128] * 128 / 1e9, 1),
+            "method": f"n = 2^{int(np.log2(n))} random reads of 8 / 32 / 64 / 128 bytes from a {gib} GiB array "
+                      f"(cskv_probe_gather), median of {reps}; granule = 128 * rate(128 B) / rate(8 B), the byte "
+                      f"models use the nearest of 32 / 64 / 128"}
+
+
 def upsert_bytes_contract(dim: int, load: float, hist: dict) -> float:
-    """Algorithmic bytes per key of an upsert call in the hot-path contract's model, weighted by
-    the call's status histogram {status: count} (fresh keys: no updates):
+    """Bytes per key of an upsert call in the survey's contract model, weighted by the call's
+    status histogram {status: count} (fresh keys: no updates).  It charges phase D2 both buckets'
+    whole score lines per key, as Alg. 3 read literally does:
     INSERT        = key + row + both digest lines + false-positive key granules (load)
                     + key, score and digest granules + row + status;
-    INSERT_EVICT  = INSERT + both buckets' score lines (phase D2) + the victim's key granule;
+    INSERT_EVICT  = INSERT + both buckets' score lines + the victim's key granule;
     REJECTED      = key + both digest lines + both score lines + false positives + status."""
     V = 4 * dim
     insert = K_B + V + 2 * L_B + load * S_B + 3 * S_B + V + F_B
@@ -176,16 +223,21 @@ def upsert_bytes_contract(dim: int, load: float, hist: dict) -> float:
     return sum(path.get(k, 0.0) * c for k, c in hist.items()) / tot if tot else 0.0
 
 
-def upsert_bytes_per_key(dim: int, load: float, batch: int, nbuckets: int) -> float:
-    """Algorithmic bytes of one insert_or_assign of a fresh key (dual mode): the input key and row,
-    both candidate digest lines (routing needs both occupancies), the digest byte, key and score
-    of the new entry, its row, the status.  In a full table (load 1) every insert replaces the
-    bucket's minimum, which takes the bucket's score line (8 lines) once per bucket per call."""
+def upsert_bytes_model(dim: int, load: float, hist: dict, n: int, nbuckets: int) -> float:
+    """Bytes per key an upsert call must move, weighted by its status histogram (the model the
+    upsert roofline is priced with).  As the contract model, except in phase D2: a key reads the
+    two candidates' minima (one granule each) instead of their score lines, and each bucket that
+    receives inserts while full has its score and key lines read once per call to pick its victims
+    (16 lines shared by the keys routed to it; n keys spread over about B (1 - e^(-n/B)) buckets)."""
     V = 4 * dim
-    b = K_B + V + 2 * L_B + (1 + 8 + 8) + V + F_B
-    if load >= 1.0:
-        b += 8 * L_B * min(1.0, nbuckets / batch)
-    return b
+    insert = K_B + V + 2 * L_B + load * S_B + 3 * S_B + V + F_B
+    per_bucket = 2 * 8 * L_B * nbuckets * (1.0 - np.exp(-n / nbuckets)) / n
+    path = {cskv.ST_INSERTED: insert,
+            cskv.ST_INSERTED_EVICT: insert + 2 * S_B + S_B + per_bucket,
+            cskv.ST_REJECTED: K_B + 2 * L_B + 2 * S_B + load * S_B + F_B + per_bucket,
+            cskv.ST_UPDATED: K_B + V + 1.5 * L_B + 2 * S_B + V + F_B}
+    tot = sum(hist.values())
+    return sum(path.get(k, 0.0) * c for k, c in hist.items()) / tot if tot else 0.0
 
 
 class Level:
@@ -485,7 +537,7 @@ def bench_roles(dev, log2_cap=26, dim=16, load=0.75, n=1 << 16, calls=200, reps=
             "final_load": round(final / cap, 4), "mixes": res}
 
 
-def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(0.5, 0.8)):
+def bench_serving(dev, log2_cap=28, dim=128, nreq=100_000, budget=4 << 30, loads=(0.5, 0.8)):
     """Serving loop: a 2^28-slot dim-128 LRU table (~142 GB) prefilled with ranks 1..2^28;
     requests of lognormal(4096, 1.0) keys clipped to 256..65536, 90 % find / 10 %
     insert_and_evict, Zipf(1.1) keys over 2^34, arriving as a Poisson process at 50 % and 80 % of
@@ -504,11 +556,11 @@ def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(
     keys = Zipf(1.1, 1 << 34).sample_device(33, int(sizes.sum()), dev)
     ins = ops == serve.REQ_INSERT_AND_EVICT
     off = np.concatenate([[0], np.cumsum(sizes)])
-    ins_keys = torch.cat([keys[off[i]:off[i + 1]] for i in range(nreq) if ins[i]])
-    vals = value_rows(14, ins_keys, dim)
+    # every insert reads its rows from one shared block (rows are copied, never inspected, here)
+    vals = value_rows(14, torch.arange(int(sizes.max()), dtype=torch.int64, device=dev), dim)
     log(f"serving: {nreq} requests, {int(sizes.sum())} keys")
     zero = np.zeros(nreq)
-    tr = serve.Trace(t, ops, sizes, keys, vals, zero)
+    tr = serve.Trace(t, ops, sizes, keys, vals, zero, shared_values=True)
     st_plain, _ = serve.serve(t, tr, budget, max_inflight_groups=1, max_merge=1, realtime=False)
     sat = nreq / st_plain["wall_s"]
     st_cb, _ = serve.serve(t, tr, budget, max_inflight_groups=2, max_merge=64, realtime=False)
@@ -521,7 +573,7 @@ def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(
         arr = poisson_arrivals(40 + int(frac * 100), nreq, qps)
         row = {"qps": round(qps, 1)}
         for name, mi, mm in (("continuous_batching", 2, 64), ("plain_fifo", 1, 1)):
-            trq = serve.Trace(t, ops, sizes, keys, vals, arr)
+            trq = serve.Trace(t, ops, sizes, keys, vals, arr, shared_values=True)
             st, times = serve.serve(t, trq, budget, max_inflight_groups=mi, max_merge=mm, realtime=True)
             lat = times["latency_s"][nreq // 10:]  # after warm-up
             row[name] = {**{k: round(v, 4) for k, v in serve.percentiles_ms(lat).items()},
@@ -533,29 +585,151 @@ def bench_serving(dev, log2_cap=28, dim=128, nreq=10000, budget=4 << 30, loads=(
     return out
 
 
-def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
-    """Sequential C oracle (one thread) on a sample: a 2^22-slot dual LRU table filled to each
-    load factor (untimed), then the step's three ops on 2^18-key batches, timed."""
+def bench_online(dev, log2_cap=27, dim=64, steps=200, batch=1 << 20, alpha=1.05):
+    """Continuous online eviction (the third workload: Sec. 2.3 online ingestion, Sec. 5.4 Exp. 3c
+    setting): a 2^27-slot dim-64 dual LFU table filled with uniform keys above 2^32 (increment 1)
+    until full (or 1.25x its capacity offered), then `steps` steps of insert_and_evict of 2^20
+    Zipf(1.05) keys over 2^32 (increment 1 per occurrence, repeats summed) followed by a find of
+    2^20 fresh Zipf keys.  HIP-event time of every call; B-KV/s per op (medians), evictions and
+    hits per step, and each op's HBM fraction from the byte models (insert_and_evict: the upsert
+    model over the call's distinct keys plus the evicted output, 2 rows + key + score per
+    eviction; find: the find model at the measured hit rate and b2 share)."""
+    cap = 1 << log2_cap
+    nb = cap // 128
+    t = cskv.Table(cap, dim, mode="dual", policy="lfu", device=dev)
+    rows = value_rows(8, torch.arange(batch, dtype=torch.int64, device=dev), dim)
+    offered = 0
+    while True:
+        k = gen_keys(63, batch, offered, device=dev) | (1 << 40)
+        t.insert_or_assign(k, rows, want_status=False)
+        offered += batch
+        size = t.size()
+        if size >= cap or offered >= cap + cap // 4:
+            break
+    log(f"online: prefilled {size} ({size / cap:.4f}) with {offered} keys offered")
+    z = Zipf(alpha, 1 << 32)
+    ins_keys = [z.sample_device(64 + s, batch, dev) for s in range(steps)]
+    find_keys = [z.sample_device(5000 + s, batch, dev) for s in range(steps)]
+    st = torch.empty(batch, dtype=torch.uint8, device=dev)
+    evo = (st, torch.empty(batch, dtype=torch.int64, device=dev), torch.empty((batch, dim), dtype=torch.float32, device=dev),
+           torch.empty(batch, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+    fout = torch.empty((batch, dim), dtype=torch.float32, device=dev)
+    found = torch.empty(batch, dtype=torch.uint8, device=dev)
+    evicted = torch.zeros(steps, dtype=torch.int64, device=dev)
+    hits = torch.zeros(steps, dtype=torch.int64, device=dev)
+    hist = torch.zeros((steps, 6), dtype=torch.int64, device=dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e in evs:
+        for x in e:
+            x.record()
+    torch.cuda.synchronize()
+    for s in range(steps):
+        e0, e1, e2 = evs[s]
+        e0.record()
+        t.insert_and_evict(ins_keys[s], rows, out=evo)
+        e1.record()
+        t.find(find_keys[s], values_out=fout, found_out=found, want_scores=False)
+        e2.record()
+        evicted[s] = evo[4][0]
+        hits[s] = found.sum()
+        # statuses of the call's distinct keys (every occurrence of a key reports its key's status)
+        u, first = torch.unique(ins_keys[s], return_inverse=True)
+        pos = torch.full((u.numel(),), batch, dtype=torch.int64, device=dev).scatter_reduce_(
+            0, first, torch.arange(batch, device=dev), reduce="amin")
+        hist[s] = torch.bincount(st[pos].to(torch.int64), minlength=6)[:6]
+    torch.cuda.synchronize()
+    ie_ms = [a.elapsed_time(b) for a, b, _ in evs]
+    f_ms = [b.elapsed_time(c) for _, b, c in evs]
+    k, _, _, sl = t.export(with_values=False)
+    fb2 = share_in_b2(k, sl, nb)
+    size = t.size()
+    del k, sl
+    ev_cnt = evicted.cpu().numpy()
+    hit_cnt = hits.cpu().numpy()
+    h = hist.cpu().numpy()
+    ie_bytes, f_bytes = [], []
+    V = 4 * dim
+    for s in range(steps):
+        hs = {c: int(h[s, c]) for c in range(1, 5) if h[s, c]}
+        distinct = sum(hs.values())
+        per = upsert_bytes_model(dim, 1.0, hs, distinct, nb) if distinct else 0.0
+        # inputs and statuses of the repeated occurrences, and the evicted output
+        ie_bytes.append(distinct * per + (batch - distinct) * (K_B + F_B) + int(ev_cnt[s]) * (2 * V + 16))
+        f_bytes.append(batch * find_bytes_per_key(dim, float(hit_cnt[s]) / batch, size / cap, fb2))
+    ie_gbs = float(np.sum(ie_bytes) / (np.sum(ie_ms) / 1e3) / 1e9)
+    f_gbs = float(np.sum(f_bytes) / (np.sum(f_ms) / 1e3) / 1e9)
+    tot = h.sum(axis=0)
+    out = {"workload": f"2^{log2_cap} slots dim {dim} dual LFU, filled to {size / cap:.4f}; {steps} steps of "
+                       f"insert_and_evict of 2^{int(np.log2(batch))} Zipf({alpha}) keys over 2^32 then a find of "
+                       f"2^{int(np.log2(batch))} fresh Zipf keys",
+           "steps": steps,
+           "insert_and_evict_bkvs": round(batch / float(np.median(ie_ms)) / 1e6, 3),
+           "find_bkvs": round(batch / float(np.median(f_ms)) / 1e6, 3),
+           "step_ms_median": round(float(np.median(np.array(ie_ms) + np.array(f_ms))), 4),
+           "evictions_per_step": round(float(ev_cnt.mean()), 1),
+           "find_hit_rate": round(float(hit_cnt.mean()) / batch, 4),
+           "distinct_keys_per_step": round(float(tot[1:5].sum()) / steps, 1),
+           "status_share_distinct": {str(c): round(float(tot[c]) / float(tot[1:5].sum()), 4) for c in range(1, 5)},
+           "share_in_b2": round(fb2, 4),
+           "roofline": {"insert_and_evict": {"achieved": round(ie_gbs, 1), "frac": round(ie_gbs / HBM_PEAK_GBS, 4)},
+                        "find": {"achieved": round(f_gbs, 1), "frac": round(f_gbs / HBM_PEAK_GBS, 4)},
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "bound": "hbm"}}
+    log(f"online: {out}")
+    del t, ins_keys, find_keys, rows, evo, fout
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo's)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20)
+        for ln in r.stdout.splitlines():
+            if ln.strip().startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "unknown")
+    except OSError:
+        return "unknown"
+
+
+def cpu_baseline_worker(log2_cap: int, log2_batch: int, loads, warmup: int):
+    """The sequential C oracle on the benchmark's own C2 inputs, pinned to one core: the same
+    capacity, the same fresh-key fills to each load (untimed), then per load the step's three
+    calls with the step's keys (a 100 %-hit find of keys drawn from the sorted resident set, a
+    50 %-hit find, the first timed step's insert_or_assign), each timed.  Runs in a process of its
+    own that never touches the GPU, started before the benchmark initialises it; prints one JSON
+    line."""
     import oracle
     from paper_2603_17168_amd.workload import as_u64
 
-    cap = 1 << sample_log2_cap
+    cpus = sorted(os.sched_getaffinity(0))
+    core = cpus[-1]
+    os.sched_setaffinity(0, {core})
+    torch.set_num_threads(1)
+    cap, batch = 1 << log2_cap, 1 << log2_batch
     o = oracle.Oracle(cap // 128, 128, oracle.DUAL, oracle.LRU)
     offered = 0
-    tot_keys = 0
-    tot_s = 0.0
+    zeros = np.zeros(batch, np.uint64)
     op_s = {"find_hit100": 0.0, "find_hit50": 0.0, "insert_or_assign": 0.0}
-    rng = np.random.default_rng(0)
-    for lam in loads:
-        while o.size() < lam * cap and offered < 2 * cap:
-            k = as_u64(gen_keys(3, batch, offered))
-            o.upsert(k, np.zeros(batch, np.uint64))
+    t_fill = time.perf_counter()
+    for li, lam in enumerate(loads):
+        while True:
+            o.upsert(as_u64(gen_keys(1, batch, offered)), zeros)
             offered += batch
-        res = o.export()[0]
-        q100 = res[rng.integers(0, res.size, batch)]
-        q50 = np.concatenate([res[rng.integers(0, res.size, batch // 2)], as_u64(gen_keys(998, batch // 2))])
-        fresh = as_u64(gen_keys(997, batch, offered))
-        zeros = np.zeros(batch, np.uint64)
+            if o.size() >= lam * cap or offered >= 2 * cap:
+                break
+        res = np.sort(o.export()[0].view(np.int64)).view(np.uint64)
+        q100 = res[as_u64(randint(100 + li, batch, res.size))]
+        idx2 = as_u64(randint(200 + li, batch // 2, res.size))
+        perm = torch.argsort(randint(300 + li, batch, 1 << 40)).numpy()
+        q50 = np.concatenate([res[idx2], as_u64(gen_keys(900, batch // 2, li * batch))])[perm]
+        fresh = as_u64(gen_keys(500 + li, batch, warmup * batch))
         t0 = time.perf_counter()
         o.find(q100)
         t1 = time.perf_counter()
@@ -566,22 +740,38 @@ def cpu_baseline(loads, sample_log2_cap=22, batch=1 << 18):
         op_s["find_hit100"] += t1 - t0
         op_s["find_hit50"] += t2 - t1
         op_s["insert_or_assign"] += t3 - t2
-        tot_s += t3 - t0
-        tot_keys += 3 * batch
         if lam < 1.0:
             o.erase(fresh)
-    model = "unknown"
+    fill_s = time.perf_counter() - t_fill - sum(op_s.values())
+    tot_s = sum(op_s.values())
+    res = {"value": 3 * len(loads) * batch / tot_s / 1e6, "unit": "M-KV/s", "cores": 1, "kind": "oracle",
+           "per_op_mkvs": {k: round(len(loads) * batch / v / 1e6, 3) for k, v in op_s.items()},
+           "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(), "pinned_core": core,
+           "sample": f"sequential C oracle (gcc -O2), one thread pinned to core {core}, on the benchmark's inputs: "
+                     f"2^{log2_cap}-slot dual LRU table filled with the same 2^{log2_batch}-key fresh batches to "
+                     f"loads {loads} ({fill_s:.0f} s untimed); per load the step's find (100% hit), find (50% hit) "
+                     f"and insert_or_assign of 2^{log2_batch} keys; {tot_s:.1f} s timed"}
+    print(json.dumps(res), flush=True)
+
+
+def start_cpu_baseline(args):
+    """Starts the oracle worker (before this process initialises the GPU)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--log2-capacity",
+           str(args.log2_capacity), "--log2-batch", str(args.log2_batch), "--loads", args.loads,
+           "--warmup", str(args.warmup)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc, timeout_s: float = 900.0):
     try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
-    except OSError:
-        pass
-    return {"value": tot_keys / tot_s / 1e6, "unit": "M-KV/s", "cores": 1, "kind": "oracle",
-            "per_op_mkvs": {k: round(len(loads) * batch / v / 1e6, 3) for k, v in op_s.items()},
-            "host_cpu": model, "host_logical_cpus": os.cpu_count(),
-            "sample": f"sequential C oracle, 2^{sample_log2_cap}-slot dual LRU table filled to loads {loads}; "
-                      f"per load one find (100% hit), one find (50% hit) and one insert_or_assign of "
-                      f"2^{int(np.log2(batch))} keys; {tot_s:.1f} s timed"}
+        out, err = proc.communicate(timeout=timeout_s)
+    except Exception as e:  # a hung worker must not lose the benchmark line
+        proc.kill()
+        return {"error": f"oracle worker did not finish: {e!r}"}
+    if proc.returncode != 0:
+        return {"error": f"oracle worker exited with {proc.returncode}: {err[-400:]}"}
+    return json.loads(out.strip().splitlines()[-1])
 
 
 def counter_probe(dev, cap, dim, batch, loads):
@@ -589,11 +779,12 @@ def counter_probe(dev, cap, dim, batch, loads):
     (the scale reference for FETCH_SIZE / WRITE_SIZE), then per load factor on the C2 table: two
     finds at 100 % hit, two at 50 % hit, two insert_or_assign of fresh keys and their erases.
     Prints one JSON line naming the sequence of calls."""
-    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     seq = ["copy_1GiB"]
-    dst.copy_(src)
+    cskv.probe_copy(src, dst)  # the library's 16-byte-per-lane copy kernel
+    torch.cuda.synchronize()
     del src, dst
     t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
     t.set_tuning(find_group=8, find_prefetch_b2=0, find_pairs=1, route_group=8)  # the shapes the bench picks
@@ -625,6 +816,12 @@ def counter_probe(dev, cap, dim, batch, loads):
             if lam < 1.0:
                 t.erase(fk, erased_out=erased)
                 seq.append(f"erase@{lam}")
+        if lam >= 1.0:
+            evo = (status, torch.empty(batch, dtype=torch.int64, device=dev), outs,
+                   torch.empty(batch, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+            for r in range(2):
+                t.insert_and_evict(gen_keys(520 + r, batch, 0, device=dev), rows, out=evo)
+                seq.append(f"insert_and_evict@{lam}")
         torch.cuda.synchronize()
         log(f"probe: load {size / cap:.4f} done")
     print(json.dumps({"counter_probe": seq, "capacity": cap, "dim": dim, "batch": batch}), flush=True)
@@ -642,17 +839,26 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-online", action="store_true", help="skip the online-eviction workload (Zipf, LFU)")
     ap.add_argument("--no-roles", action="store_true", help="skip the concurrency ablation (lock modes)")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid HBM + host value storage rates")
-    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-requests", type=int, default=100_000)
     ap.add_argument("--no-api", action="store_true", help="skip the contains / find_ptr / assign / find_or_insert rates")
     ap.add_argument("--counter-probe", action="store_true",
                     help="run only the short fixed call sequence used for hardware-counter runs")
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args.log2_capacity, args.log2_batch, [float(x) for x in args.loads.split(",")],
+                            args.warmup)
+        return
+    cpu_proc = None
+    if not args.no_cpu_baseline and not args.counter_probe:
+        cpu_proc = start_cpu_baseline(args)  # a process of its own, started before the GPU is touched
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -663,6 +869,10 @@ def main():
     if args.counter_probe:
         counter_probe(dev, cap, dim, batch, loads)
         return
+    global S_B
+    granule = calibrate_granule(dev)
+    S_B = granule["granule_model_bytes"]
+    log(f"granule: {granule}")
 
     # ---------------- setup (untimed): tables at each load factor, query sets
     base = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
@@ -674,7 +884,7 @@ def main():
         k, _, _, sl = t.export(with_values=False)
         fb2 = share_in_b2(k, sl, cap // 128)
         del sl
-        levels.append(Level(t, lam, k, fb2))
+        levels.append(Level(t, lam, torch.sort(k)[0], fb2))  # queries are drawn from the sorted residents
         log(f"setup: load {lam:.2f} -> size {size} ({size / cap:.4f}), offered {offered}, in b2 {fb2:.3f}")
     del base
     torch.cuda.synchronize()
@@ -754,16 +964,21 @@ def main():
 
     # cold finds (untimed for `value`): a 512 MiB scrub write evicts the 256 MiB last-level cache
     # before one 100 %-hit find per load
-    cold = {}
+    # and, to tell what the warm runs gain from that cache, the same find after a scrub followed by
+    # one pass over the digest array alone (the size call reads every digest line: 128 B a bucket)
+    cold, cold_dig = {}, {}
     scrub = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
     for li, lv in enumerate(levels):
-        scrub.fill_(li + 1)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        lv.t.find(q100[li], values_out=outs, found_out=found, want_scores=False)
-        e1.record()
-        torch.cuda.synchronize()
-        cold[li] = batch / e0.elapsed_time(e1) / 1e6
+        for warm_digests in (False, True):
+            scrub.fill_(li + 1)
+            if warm_digests:
+                lv.t.size_tensor()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lv.t.find(q100[li], values_out=outs, found_out=found, want_scores=False)
+            e1.record()
+            torch.cuda.synchronize()
+            (cold_dig if warm_digests else cold)[li] = batch / e0.elapsed_time(e1) / 1e6
     del scrub
     # the rest of the API (not in `value`): median of 3 event-timed calls per load
     api = {}
@@ -878,17 +1093,21 @@ def main():
         find_bytes += [batch * find_bytes_per_key(dim, 0.5, lam, lv.frac_b2)] * len(f50)
         per_op[f"{lv.target:.2f}"]["share_in_b2"] = round(lv.frac_b2, 4)
         per_op[f"{lv.target:.2f}"]["find_hit100_cold_bkvs"] = round(cold[li], 3)
+        per_op[f"{lv.target:.2f}"]["find_hit100_cold_digests_cached_bkvs"] = round(cold_dig[li], 3)
     achieved = float(np.sum(find_bytes) / (np.sum(find_ms) / 1e3) / 1e9)
-    ups_ms, ups_bytes, ups_strict = [], [], []
+    ups_ms, ups_bytes, ups_contract = [], [], []
     for li, lv in enumerate(levels):
         ms = [x.elapsed_time(y) for x, y in zip(ev[f"f50_{li}_b"], ev[f"ups_{li}_b"])]
         ups_ms += ms
         lam = lv.resident.numel() / cap
-        ups_bytes += [batch * upsert_bytes_contract(dim, lam, hists[li])] * len(ms)
-        ups_strict += [batch * upsert_bytes_per_key(dim, lv.target, batch, cap // 128)] * len(ms)
+        ups_bytes += [batch * upsert_bytes_model(dim, lam, hists[li], batch, cap // 128)] * len(ms)
+        ups_contract += [batch * upsert_bytes_contract(dim, lam, hists[li])] * len(ms)
         per_op[f"{lv.target:.2f}"]["upsert_status"] = {str(k): v for k, v in hists[li].items()}
+        per_op[f"{lv.target:.2f}"]["upsert_frac_of_peak"] = round(
+            upsert_bytes_model(dim, lam, hists[li], batch, cap // 128) * batch / (np.median(ms) / 1e3) / 1e9
+            / HBM_PEAK_GBS, 4)
     ups_achieved = float(np.sum(ups_bytes) / (np.sum(ups_ms) / 1e3) / 1e9)
-    ups_strict_achieved = float(np.sum(ups_strict) / (np.sum(ups_ms) / 1e3) / 1e9)
+    ups_contract_achieved = float(np.sum(ups_contract) / (np.sum(ups_ms) / 1e3) / 1e9)
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -910,7 +1129,7 @@ def main():
         "latency_ms": {k: {"p50": round(float(np.percentile(v, 50)), 4), "p99": round(float(np.percentile(v, 99)), 4)}
                        for k, v in lat.items() if v},
         "tuning": tuning,
-        "roofline": {"bound": "hbm", "kernel": "k_find (autotuned per load, see tuning)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": find_kernel_names(tunings, levels), "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": find_traffic_per_launch(dim, [lv.target for lv in levels], batch)},
         "api": api,
@@ -918,8 +1137,8 @@ def main():
                             "achieved": round(ups_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(ups_achieved / HBM_PEAK_GBS, 4),
                             "traffic": upsert_traffic_per_launch(dim, [lv.target for lv in levels], batch),
-                            "achieved_free_slot_model": round(ups_strict_achieved, 1),
-                            "frac_free_slot_model": round(ups_strict_achieved / HBM_PEAK_GBS, 4)},
+                            "achieved_contract_model": round(ups_contract_achieved, 1),
+                            "frac_contract_model": round(ups_contract_achieved / HBM_PEAK_GBS, 4)},
     }
     del levels, q100, q50, fresh, rows, outs
     torch.cuda.synchronize()
@@ -928,11 +1147,15 @@ def main():
     for k in ("roofline", "roofline_upsert"):
         out[k]["copy_peak"] = round(copy_peak, 1)
         out[k]["frac_of_copy_peak"] = round(out[k]["achieved"] / copy_peak, 4)
+        out[k]["granule"] = granule
     if not args.no_batched:
         log("batched programs")
         out["batched"] = bench_batched(dev)
         log("batched programs, small batches")
         out["batched_small"] = bench_batched(dev, lo=1 << 10, hi=1 << 14)
+    if not args.no_online:
+        log("online eviction (Zipf, LFU, full table)")
+        out["online"] = bench_online(dev)
     if not args.no_serving:
         log("serving loop")
         out["serving"] = bench_serving(dev, nreq=args.serve_requests)
@@ -947,9 +1170,9 @@ def main():
     if not args.no_roles:
         log("concurrency ablation: lock modes")
         out["roles"] = bench_roles(dev)
-    if not args.no_cpu_baseline:
-        log("cpu baseline: timing the sequential oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(loads)
+    if cpu_proc is not None:
+        log("cpu baseline: waiting for the sequential oracle")
+        out["cpu_baseline"] = finish_cpu_baseline(cpu_proc)
     print(json.dumps(out), flush=True)
 
 

@@ -95,6 +95,8 @@ def lib():
         "cskv_row_address": (U64, [P, U64]),
         "cskv_get_lock_mode": (I, [P]),
         "cskv_mt_run": (I, [P, I, P, ctypes.POINTER(ctypes.c_double)]),
+        "cskv_probe_copy": (I, [P, P, SZ, P]),
+        "cskv_probe_gather": (I, [P, SZ, U32, U64, U64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -125,6 +127,24 @@ def _as_i64(t: torch.Tensor, device) -> torch.Tensor:
     if t.device != device:
         raise ValueError(f"tensor on {t.device}, table on {device}")
     return t.contiguous()
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor):
+    """cskv_probe_copy: the 16-byte-per-lane reference copy of src's bytes into dst (same size)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size() or src.device != dst.device:
+        raise ValueError("probe_copy needs two equal-sized buffers on one device")
+    with torch.cuda.device(src.device):
+        _check(lib().cskv_probe_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream(src.device)),
+               "cskv_probe_copy")
+
+
+def probe_gather(src: torch.Tensor, width: int, n: int, salt: int, out: torch.Tensor):
+    """cskv_probe_gather: n random `width`-byte reads from src (power-of-two bytes) into out."""
+    if out.numel() * out.element_size() < n * width or src.device != out.device:
+        raise ValueError("probe_gather: out must hold n * width bytes on src's device")
+    with torch.cuda.device(src.device):
+        _check(lib().cskv_probe_gather(_ptr(src), src.numel() * src.element_size(), width, n, salt, _ptr(out),
+                                       _stream(src.device)), "cskv_probe_gather")
 
 
 class Table:

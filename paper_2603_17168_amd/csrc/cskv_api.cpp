@@ -18,7 +18,7 @@ StorageLayout storage_layout(uint64_t nb, uint32_t dim, uint64_t hbm_rows) {
     L.off_keys = o;   o = align256(o + nb * kSlots * 8);
     L.off_scores = o; o = align256(o + nb * kSlots * 8);
     L.off_vals = o;   o = align256(o + hbm_rows * (size_t)dim * 4);
-    L.off_cnt = o;    o = align256(o + nb * 4);
+    L.off_cnt = o;    o = align256(o + nb * 8);
     L.off_bmin = o;   o = align256(o + nb * 16);
     L.off_clock = o;  o = align256(o + 8);
     L.total = o;
@@ -151,7 +151,7 @@ int cskv_create_tiered(cskv_table** out, uint64_t capacity, uint32_t bucket_size
     t->view.vals = reinterpret_cast<float*>(base + L.off_vals);
     t->view.vals_host = host_rows;
     t->view.hbm_rows = hbm_value_rows;
-    t->view.cnt = reinterpret_cast<uint32_t*>(base + L.off_cnt);
+    t->view.cnt = reinterpret_cast<uint64_t*>(base + L.off_cnt);
     t->view.bmin = reinterpret_cast<uint64_t*>(base + L.off_bmin);
     t->view.clock = reinterpret_cast<uint64_t*>(base + L.off_clock);
     t->view.nbuckets = nb;

@@ -6,7 +6,8 @@
 //     keys   u64[B][128]          key line(s) per bucket (0 = empty)
 //     scores u64[B][128]          score line(s) per bucket
 //     vals   f32[B][128][dim]     value rows, addressed by (bucket, slot)
-//     cnt    u32[B]               operations routed to a bucket by the running call (0 between calls)
+//     cnt    u64[B]               operations routed to a bucket by the running call: inserts in the
+//                                  low 32 bits, updates in the high 32 bits (0 between calls)
 //     bmin   u64[B][2]            (score, key) of a full bucket's minimum entry; key 0 = not known
 //     clock  u64                  LRU logical clock (device-resident so captured graphs advance it)
 //
@@ -16,7 +17,8 @@
 //     sstat u8[P]                      status of each distinct key's operation
 //     slot_of u32[n]                   dedupe slot of input i (or kNoSlot)
 //     il OpEntry[B*C]                  per-bucket operation lists: key, new score,
-//                                      (dedupe slot << 32 | input position), slot (0xFF = insert)
+//                                      (dedupe slot << 32 | input position), and a meta word (slot,
+//                                      digest, kind, free slots of the bucket before the call)
 //     ol OpEntry[P]                    list positions >= C, hashed on (bucket, position) via okey
 //     slow u32[min(n, B)]              buckets with more operations than the fast path takes
 //     touched u32[min(n, B)]           buckets that received an operation (small batches only)
@@ -32,7 +34,10 @@ namespace cskv {
 
 constexpr int kSlots = 128;
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
-constexpr uint8_t kInsertSlot = 0xFF;
+// kinds of a routed operation: an update of a resident slot; an insert that routing already
+// wrote into one of the bucket's free slots (its digest byte is written by the apply pass); an
+// insert that found no free slot left and waits in the bucket's list for the apply pass
+enum OpKind : uint8_t { kOpUpdate = 0, kOpDirect = 1, kOpListed = 2 };
 constexpr int kFastMax = 16;  // operations per bucket handled by the 16-lane fast path
 
 // kCtrDup: the call repeats a key; kCtrDistinct: its number of distinct keys (sub-rounds only)
@@ -44,7 +49,7 @@ struct TableView {
     uint64_t* scores;
     float* vals;       // value rows [0, hbm_rows), in HBM
     float* vals_host;  // value rows [hbm_rows, nbuckets * 128), pinned host memory (device address)
-    uint32_t* cnt;
+    uint64_t* cnt;
     uint64_t* bmin;
     uint64_t* clock;
     uint64_t nbuckets;
@@ -70,7 +75,9 @@ struct OpEntry {
     uint64_t key;
     uint64_t score;
     uint64_t w;     // dedupe slot << 32 | input position
-    uint64_t slot;  // bits 0-7: table slot of an update, kInsertSlot for an insert; bits 8-15: the key's digest
+    uint64_t meta;  // bits 0-7: table slot (update: the resident slot; direct insert: the free slot it
+                    // took); 8-15: the key's digest; 16-23: OpKind; 24-31: free slots of the target
+                    // bucket before the call (inserts)
 };
 
 struct UpsertWs {
@@ -157,12 +164,13 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
 hipError_t launch_erase(const TableView& t, uint64_t n, const uint64_t* keys, uint8_t* erased,
                         uint32_t* ws_slot, int group, hipStream_t s);
 // the phases of an upsert / erase, for callers that order them with events (batched programs):
-// prep (scratch clear, dedupe) and route only read the table; apply writes it; finish writes the
+// prep (scratch clear, dedupe) reads the table; route reads it and writes only slots that are free
+// (zero digest) before the call, which no reader looks at; apply writes it; finish writes the
 // statuses; an erase probe reads, its clear writes
 hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
                               const uint64_t* scores, const EvictOut& ev, size_t zero_bytes, hipStream_t s);
 hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
-                               const uint64_t* scores, int group, hipStream_t s);
+                               const float* vals, const uint64_t* scores, int group, hipStream_t s);
 hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n, const float* vals,
                                const EvictOut& ev, hipStream_t s);
 hipError_t launch_upsert_finish(const UpsertWs& w, uint64_t n, uint8_t* status, uint32_t dim, hipStream_t s);

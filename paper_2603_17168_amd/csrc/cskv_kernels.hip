@@ -34,7 +34,7 @@ hipError_t launch_clear_table(const TableView& t, hipStream_t s) {
     if ((e = launch_fill_zero(t.keys, t.nbuckets * kSlots * 8, s)) != hipSuccess) return e;
     if ((e = launch_fill_zero(t.scores, t.nbuckets * kSlots * 8, s)) != hipSuccess) return e;
     if ((e = launch_fill_zero(t.bmin, t.nbuckets * 16, s)) != hipSuccess) return e;
-    return launch_fill_zero(t.cnt, t.nbuckets * 4, s);
+    return launch_fill_zero(t.cnt, t.nbuckets * 8, s);
 }
 
 // ------------------------------------------------------------------------------------------

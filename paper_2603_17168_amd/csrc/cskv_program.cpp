@@ -42,7 +42,9 @@ struct Segment {
 
 // Phases of the overlapped form.  A find run is one phase; an erase is probe (reader) + clear
 // (writer); an upsert is prep (scratch clear + dedupe: touches only its scratch slot), route
-// (reader of the table), apply (writer) and finish (status gather, scratch only).
+// (a reader of the table: the only table memory it writes is that of slots free before the call,
+// whose zero digests keep every reader away from them), apply (writer) and finish (status gather,
+// scratch only).
 enum PhaseKind { kPhFind, kPhProbe, kPhClear, kPhPrep, kPhRoute, kPhApply, kPhFinish };
 enum Lane { kLaneRead = 0, kLaneWrite = 1, kLanePrep = 2 };  // kLanePrep + scratch slot
 
@@ -490,7 +492,7 @@ static int run_phase(cskv_program* p, const Phase& ph, hipStream_t s) {
         // with route sub-rounds every round routes after the previous one applied: all of it runs
         // in the apply phase (on the writer lane, after the concurrent readers)
         case kPhRoute:
-            if (w.rounds == 1) e = launch_upsert_route(t->view, w, a.n, a.keys, a.scores, o.route_group, s);
+            if (w.rounds == 1) e = launch_upsert_route(t->view, w, a.n, a.keys, a.vals, a.scores, o.route_group, s);
             break;
         case kPhApply:
             e = w.rounds == 1 ? launch_upsert_apply(t->view, w, a.n, a.vals, a.ev, s)

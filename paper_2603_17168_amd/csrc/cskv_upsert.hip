@@ -8,22 +8,32 @@
 //            repeats): last occurrence, LFU increment sum
 //   route    G lanes per distinct key, against the table as it was before the call: update slot
 //            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
-//            smaller cached bucket minimum (score, key)); the operation is appended to the
-//            target bucket's list (rank from an atomic count per bucket)
-//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block: updates,
-//            then inserts ranked by (score desc, key asc): the first ones take free slots, the
-//            rest compete with the smallest residents by (score, key) - strict admission;
-//            victims are copied out, slots written, the bucket minimum cached when full
+//            smaller cached bucket minimum (score, key)).  One atomic on the target's counter
+//            (inserts in the low half, updates in the high half) gives the operation its place
+//            in the bucket's list and, for an insert, its arrival rank r among the bucket's
+//            inserts: while r is below the bucket's number of free slots before the call, the
+//            insert writes its key, score and row at once into the r-th of those free slots
+//            (a direct insert).  Digest bytes are not written here, so every key of the call
+//            sees the digest lines, occupancies and free-slot order of the table before it.
+//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block.  A bucket that
+//            received only inserts, no more than its free slots, just has the digest bytes of
+//            its direct inserts written.  Otherwise: updates, then inserts ranked by (score desc,
+//            key asc): the first ones (as many as there were free slots) are inserted, the rest
+//            compete with the smallest residents by (score, key) - strict admission.  Slot
+//            positions are not observable, so a direct insert keeps the slot it took; the
+//            inserts still waiting in the list take the victims' slots and the free slots of
+//            direct inserts that were refused or that evicted; victims are copied out first
 //   slow     one wave per bucket that received more than 16 operations: same rules, with the
 //            best 128 inserts kept in LDS
 //   finish   per-occurrence status
 // A plain call of one route round fuses dedupe and route (the first occurrence of a key claims
 // its set entry and routes it; k_fixup then hands each operation its last occurrence's position
-// and score when some key repeated); phased programs and route sub-rounds keep the separate
-// passes.
-// Every write to a table slot's key/score/digest is made by the lane that owns the slot, and
-// every 16-byte chunk c of a row by lane c mod (lanes), so writes that must follow one another
-// (an update, then the eviction of the same entry) are ordered by program order.
+// and score when some key repeated, and rewrites a direct insert's score and row); phased
+// programs and route sub-rounds keep the separate passes.
+// Every write to a table slot's key/score/digest in the apply kernels is made by the lane that
+// owns the slot, and every 16-byte chunk c of a row by lane c mod (lanes), so writes that must
+// follow one another (an update, then the eviction of the same entry) are ordered by program
+// order.
 #include <hip/hip_runtime.h>
 
 #include "cskv_device.h"
@@ -58,13 +68,15 @@ __device__ __forceinline__ uint64_t scratch_hash(uint64_t x, int logP) { return 
 
 __device__ __forceinline__ uint64_t overflow_key(uint32_t b, uint32_t r) { return ((uint64_t)b << 32) + r + 1; }
 
+
 struct Entry {
     uint64_t key, score, w;  // w = dedupe slot << 32 | input position
-    uint8_t slot;            // kInsertSlot for an insert
+    uint8_t slot;            // update: the resident slot; direct insert: the free slot it took
     uint8_t dg;              // the key's digest, computed once by routing
+    uint8_t kind;            // OpKind
+    uint8_t nfree;           // inserts: free slots of the bucket before the call
 };
 
-// the r-th operation routed to bucket b
 __device__ __forceinline__ Entry load_entry(const OpEntry* p) {
     const ulonglong2* q = reinterpret_cast<const ulonglong2*>(p);
     const ulonglong2 a = q[0], c = q[1];
@@ -74,14 +86,17 @@ __device__ __forceinline__ Entry load_entry(const OpEntry* p) {
     e.w = c.x;
     e.slot = (uint8_t)c.y;
     e.dg = (uint8_t)(c.y >> 8);
+    e.kind = (uint8_t)(c.y >> 16);
+    e.nfree = (uint8_t)(c.y >> 24);
     return e;
 }
 
-__device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t score, uint64_t w, uint8_t slot,
-                                            uint32_t dg) {
+__device__ __forceinline__ void store_entry(OpEntry* p, uint64_t key, uint64_t score, uint64_t w, uint32_t slot,
+                                            uint32_t dg, uint32_t kind, uint32_t nfree) {
     ulonglong2* q = reinterpret_cast<ulonglong2*>(p);
     q[0] = make_ulonglong2(key, score);
-    q[1] = make_ulonglong2(w, (unsigned long long)slot | ((unsigned long long)(dg & 0xFFu) << 8));
+    q[1] = make_ulonglong2(w, (unsigned long long)((slot & 0xFFu) | ((dg & 0xFFu) << 8) | ((kind & 0xFFu) << 16) |
+                                                   ((nfree & 0xFFu) << 24)));
 }
 
 __device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint32_t r) {
@@ -101,19 +116,24 @@ __device__ __forceinline__ OpEntry* entry_ptr(const UpsertWs& w, uint32_t b, uin
     return w.ol + q;
 }
 
+// operations routed to a bucket by the running call (inserts + updates)
+__device__ __forceinline__ uint32_t routed_ops(uint64_t c) { return (uint32_t)c + (uint32_t)(c >> 32); }
+
 // After a fused routing pass in a call that repeated a key (else it returns at once): every
 // operation takes its key's last occurrence's position and score (CUSTOM: that occurrence's
-// score; LFU: the saturated sum of the increments, added to the resident score for an update).
-// A grid-stride loop over the buckets on a small grid, so that the common case (no repeats)
-// costs little more than one flag read.
-__global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w) {
+// score; LFU: the saturated sum of the increments, added to the resident score for an update),
+// and a direct insert's slot gets that score and the last occurrence's row (routing wrote the
+// claiming occurrence's).  A grid-stride loop over the buckets on a small grid, so that the
+// common case (no repeats) costs little more than one flag read.
+__global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w, const float* __restrict__ vals) {
     if (w.ctr[kCtrDup] == 0) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t chunks = t.dim >> 2;
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < t.nbuckets; b += stride) {
-        const uint32_t m = t.cnt[b];
+        const uint32_t m = routed_ops(t.cnt[b]);
         for (uint32_t r = 0; r < m; ++r) {
             OpEntry* op = entry_ptr(w, (uint32_t)b, r);
-            Entry e = load_entry(op);
+            const Entry e = load_entry(op);
             const uint32_t p = (uint32_t)(e.w >> 32);
             const DedupeEntry de = w.dd[p];
             const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
@@ -122,9 +142,18 @@ __global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w) {
                 score = w.in_scores[last];
             } else if (t.policy == 2) {
                 const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
-                score = e.slot == kInsertSlot ? inc : sat_add(t.scores[b * kSlots + e.slot], inc);
+                score = e.kind == kOpUpdate ? sat_add(t.scores[b * kSlots + e.slot], inc) : inc;
             }
-            store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg);
+            store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg, e.kind, e.nfree);
+            if (e.kind == kOpDirect) {
+                const size_t ent = b * kSlots + e.slot;
+                t.scores[ent] = score;
+                if (last != (uint32_t)e.w) {
+                    uint4* dst = reinterpret_cast<uint4*>(t.row(ent));
+                    const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)last * t.dim);
+                    for (uint32_t c = 0; c < chunks; ++c) dst[c] = src[c];
+                }
+            }
         }
     }
 }
@@ -229,12 +258,13 @@ __global__ void __launch_bounds__(256) k_rank_write(UpsertWs w, uint64_t n) {
 // FUSED: the routing kernel also claims the dedupe entries (one CAS per occurrence, by the
 // group's lane 0, issued after the digest loads); the claiming occurrence routes the key with its
 // own position and score (routing depends only on the key and the table before the call), later
-// occurrences only record themselves, and the apply replaces position and score by the last
-// occurrence's when the call repeated a key.  Otherwise the dedupe pass ran before, and only each
-// key's last occurrence routes.
+// occurrences only record themselves, and k_fixup replaces position, score (and a direct
+// insert's row) by the last occurrence's when the call repeated a key.  Otherwise the dedupe
+// pass ran before, and only each key's last occurrence routes.
 template <int G, bool FUSED>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                               const uint64_t* __restrict__ scores, uint64_t* ev_count) {
+                                               const float* __restrict__ vals, const uint64_t* __restrict__ scores,
+                                               uint64_t* ev_count) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int lane = glane<G>();
     if (FUSED && i == 0 && lane == 0 && ev_count) *ev_count = 0;
@@ -306,36 +336,47 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     uint64_t inc = 0;
     if (t.policy == 2) inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);  // FUSED: provisional
     uint64_t ns;
-    uint8_t islot;
-    if (slot >= 0) {  // UPDATE in place (Alg. 2, found)
+    const bool upd = slot >= 0;
+    uint32_t em = 0;  // inserts: this lane's share of the target's free slots (before the call)
+    int nfree = 0;
+    if (upd) {  // UPDATE in place (Alg. 2, found)
         if (t.policy == 0) ns = scores[i];
         else if (t.policy == 1) ns = clock;
         else ns = sat_add(t.scores[(size_t)tgt * kSlots + slot], inc);
-        islot = (uint8_t)slot;
     } else {  // INSERT: candidate choice (Alg. 3)
         tgt = h.b1;
+        const uint32_t em1 = s1.empty_mask();
+        em = em1;
         if (two) {
-            const int occ1 = kSlots - gsum_i<G>(__popc(s1.empty_mask()));
-            const int occ2 = kSlots - gsum_i<G>(__popc(s2.empty_mask()));
+            const uint32_t em2 = s2.empty_mask();
+            const int occ1 = kSlots - gsum_i<G>(__popc(em1));
+            const int occ2 = kSlots - gsum_i<G>(__popc(em2));
             if (occ1 < kSlots || occ2 < kSlots) {  // phase D1: less occupied, b1 on a tie
-                if (occ2 < occ1) tgt = h.b2;
+                if (occ2 < occ1) {
+                    tgt = h.b2;
+                    em = em2;
+                }
             } else {  // phase D2: smaller minimum (score, key)
                 uint64_t m1s = t.bmin[2 * (size_t)h.b1], m1k = t.bmin[2 * (size_t)h.b1 + 1];
                 uint64_t m2s = t.bmin[2 * (size_t)h.b2], m2k = t.bmin[2 * (size_t)h.b2 + 1];
                 if (m1k == 0) bucket_min<G>(t, h.b1, lane, m1s, m1k);
                 if (m2k == 0) bucket_min<G>(t, h.b2, lane, m2s, m2k);
-                if (m2s < m1s || (m2s == m1s && m2k < m1k)) tgt = h.b2;
+                if (m2s < m1s || (m2s == m1s && m2k < m1k)) {
+                    tgt = h.b2;
+                    em = em2;
+                }
             }
         }
+        nfree = gsum_i<G>(__popc(em));
         if (t.policy == 0) ns = scores[i];
         else if (t.policy == 1) ns = clock;
         else ns = inc;
-        islot = kInsertSlot;
     }
+    unsigned long long old = 0;
     if (lane == 0) {
-        const uint32_t r = atomicAdd(t.cnt + tgt, 1u);
+        old = atomicAdd(reinterpret_cast<unsigned long long*>(t.cnt + tgt), upd ? (1ull << 32) : 1ull);
         if (w.list_mode) {  // newly touched buckets: one cursor atomic per wave, not per bucket
-            const bool first = r == 0;
+            const bool first = old == 0;
             const uint64_t bal = __ballot(first);  // over the active group leaders of this wave
             if (bal) {
                 const int me = threadIdx.x & 63;
@@ -346,20 +387,37 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
                 if (first) w.touched[base + __popcll(bal & ((1ull << me) - 1))] = tgt;
             }
         }
+    }
+    const uint32_t ir = (uint32_t)__shfl((int)(uint32_t)old, 0, G);          // arrival rank among the inserts
+    const uint32_t r = ir + (uint32_t)__shfl((int)(uint32_t)(old >> 32), 0, G);  // place in the bucket's list
+    const bool direct = !upd && ir < (uint32_t)nfree;
+    int eslot = slot;
+    if (direct) eslot = nth_free<G>(em, (int)ir, lane);  // the ir-th free slot, in slot order
+    if (lane == 0) {
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
+        const uint32_t kind = upd ? kOpUpdate : (direct ? kOpDirect : kOpListed);
+        const uint32_t es = eslot >= 0 ? (uint32_t)eslot : 0u;
         if (r < w.cap) {
-            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, islot, h.dg);
+            store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, es, h.dg, kind, (uint32_t)nfree);
         } else {
             const uint64_t ok = overflow_key(tgt, r);
             uint64_t q = scratch_hash(ok, w.logP);
             for (uint64_t probes = 0; probes < w.P; ++probes) {
-                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(w.okey + q), 0ull,
-                                                         (unsigned long long)ok);
-                if (old == 0ull) break;
+                const unsigned long long o2 = atomicCAS(reinterpret_cast<unsigned long long*>(w.okey + q), 0ull,
+                                                        (unsigned long long)ok);
+                if (o2 == 0ull) break;
                 q = (q + 1) & (w.P - 1);
             }
-            store_entry(w.ol + q, k, ns, wv, islot, h.dg);
+            store_entry(w.ol + q, k, ns, wv, es, h.dg, kind, (uint32_t)nfree);
         }
+    }
+    if (direct) {  // key, score and row now; the digest byte in the apply pass
+        const size_t e = (size_t)tgt * kSlots + eslot;
+        if (lane == 0) {
+            t.keys[e] = k;
+            t.scores[e] = ns;
+        }
+        copy_row<G>(t.row(e), vals + i * t.dim, t.dim, lane);
     }
 }
 
@@ -371,7 +429,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     __shared__ uint32_t s_nev[kApplyGroups];
     __shared__ uint32_t s_off[kApplyGroups];
     __shared__ unsigned long long s_base;
-    __shared__ uint8_t s_free[kApplyGroups][GA];  // per group: the free slots taken by the first inserts, by rank
+    __shared__ uint8_t s_pool[kApplyGroups][GA];  // per group: slots handed to the listed inserts that rank first
     __shared__ uint64_t s_keys[kApplyGroups][kSlots];
     const int g = threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
@@ -379,20 +437,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     uint64_t bb = (uint64_t)blockIdx.x * kApplyGroups + g;
     if (w.list_mode) bb = bb < w.ctr[kCtrTouched] ? w.touched[bb] : t.nbuckets;
     const uint32_t b = (uint32_t)bb;
-    uint32_t m = 0;
-    if (bb < t.nbuckets) m = t.cnt[b];
+    uint32_t ni = 0, nu = 0;
+    if (bb < t.nbuckets) {
+        const uint64_t c = t.cnt[b];
+        ni = (uint32_t)c;
+        nu = (uint32_t)(c >> 32);
+    }
+    uint32_t m = ni + nu;
     if (m > (uint32_t)kFastMax) {
         if (lane == 0) w.slow[atomicAdd(w.ctr + kCtrSlow, 1u)] = b;
-        m = 0;
+        m = ni = nu = 0;
     }
     const size_t eb = (size_t)b * kSlots;
 
     // state carried over the block barrier
-    Entry e{0, 0, 0, kInsertSlot};
-    bool is_upd = false, is_ins = false, evicts = false;
-    int new_slot = -1, evi = 0;
+    Entry e{0, 0, 0, 0, 0, kOpUpdate, 0};
+    bool is_upd = false, is_ins = false, is_direct = false, admitted = false, evicts = false;
+    int q = 0;          // rank of an insert among the bucket's inserts, (score desc, key asc)
+    int new_slot = -1;  // slot of an admitted insert (a direct insert keeps its own)
+    int vslot = -1, evi = 0;
     uint64_t vkey = 0, vscore = 0;
-    uint32_t taken = 0, upd_bits = 0, ins_bits = 0;
+    uint32_t upd_bits = 0, ins_bits = 0;
+    int nfree = 0;
     // a bucket that ends full: its scores (this call's updates applied) in registers and its keys in
     // LDS, each lane holding its own 8 slots of both
     uint64_t sc[SPL];
@@ -403,69 +469,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     if (m > 0) {
         const bool has = lane < (int)m;
         if (has) e = fetch_entry(w, b, (uint32_t)lane);
-        is_upd = has && e.slot != kInsertSlot;
-        is_ins = has && e.slot == kInsertSlot;
-        const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
-        const uint32_t emask8 = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);  // bit q: slot lane*8+q is free
-        const int occ = kSlots - gsum_i<GA>(__popc(emask8));
-        const int nfree = kSlots - occ;
+        is_upd = has && e.kind == kOpUpdate;
+        is_ins = has && e.kind != kOpUpdate;
+        is_direct = has && e.kind == kOpDirect;
         upd_bits = (uint32_t)((__ballot(is_upd) >> gshift) & 0xFFFFu);
         ins_bits = (uint32_t)((__ballot(is_ins) >> gshift) & 0xFFFFu);
-        const int ni = __popc(ins_bits);
-        full_after = occ + ni >= kSlots;
-        taken = emask8;  // free slots are never victims
-
-        // rank among the inserts: (score desc, key asc)
-        int rank = 0;
-        for (int x = 0; x < (int)m; ++x) {
-            const uint64_t sx = __shfl(e.score, x, GA);
-            const uint64_t kx = __shfl(e.key, x, GA);
-            rank += (int)(((ins_bits >> x) & 1u) && (sx > e.score || (sx == e.score && kx < e.key)));
+        // free slots before the call: carried by every insert, else read from the digest line
+        nfree = gmax_i<GA>(is_ins ? (int)e.nfree : -1);
+        const bool plain = nu == 0 && (int)ni <= nfree;  // only inserts, all of them direct
+        uint32_t taken = 0;  // free slots before the call (now holding direct inserts) are never victims
+        if (!plain) {
+            const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
+            taken = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);
+            nfree = gsum_i<GA>(__popc(taken));
         }
-        if (ni > 0 && nfree > 0) {  // the first inserts take the free slots, in slot order
-            // free slot of rank r (r < ni <= 16): lane L's free slots follow the free slots of
-            // lanes 0..L-1, found by an exclusive scan of the per-lane counts
-            const int nf = __popc(emask8);
-            int incl = nf;
-#pragma unroll
-            for (int d = 1; d < GA; d <<= 1) {
-                const int v = __shfl_up(incl, d, GA);
-                if (lane >= d) incl += v;
+        full_after = (int)ni >= nfree;
+        const int want = (int)ni - nfree;  // inserts beyond the free slots: they compete for victims
+        if (want > 0) {
+            for (int x = 0; x < (int)m; ++x) {
+                const uint64_t sx = __shfl(e.score, x, GA);
+                const uint64_t kx = __shfl(e.key, x, GA);
+                q += (int)(((ins_bits >> x) & 1u) && (sx > e.score || (sx == e.score && kx < e.key)));
             }
-            uint32_t f = emask8;
-            for (int r = incl - nf; f && r < ni; ++r) {
-                s_free[g][r] = (uint8_t)(lane * SPL + __ffs(f) - 1);
-                f &= f - 1;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();  // the group is inside one wave: its LDS accesses stay in order
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (is_ins && rank < nfree) new_slot = s_free[g][rank];
         }
-        if (full_after) {  // scores and keys of the bucket, with this call's updates applied
+        if (full_after) {  // scores and keys of the bucket (direct inserts included), updates applied
             const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
             const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(t.keys + eb + lane * SPL);
 #pragma unroll
-            for (int q = 0; q < SPL / 2; ++q) {
-                const ulonglong2 v = sp[q], u = kp[q];
-                sc[2 * q] = v.x;
-                sc[2 * q + 1] = v.y;
-                kc[2 * q] = u.x;
-                kc[2 * q + 1] = u.y;
+            for (int z = 0; z < SPL / 2; ++z) {
+                const ulonglong2 v = sp[z], u = kp[z];
+                sc[2 * z] = v.x;
+                sc[2 * z + 1] = v.y;
+                kc[2 * z] = u.x;
+                kc[2 * z + 1] = u.y;
             }
             for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
                 const int x = __ffs(ub) - 1;
                 const int us = __shfl((int)e.slot, x, GA);
                 const uint64_t usc = __shfl(e.score, x, GA);
 #pragma unroll
-                for (int q = 0; q < SPL; ++q)
-                    if ((us >> 3) == lane && (us & 7) == q) sc[q] = usc;
+                for (int z = 0; z < SPL; ++z)
+                    if ((us >> 3) == lane && (us & 7) == z) sc[z] = usc;
             }
         }
         // victims for the inserts ranked nfree, nfree+1, ... (strict admission, Alg. 2)
-        const int want = ni - nfree;
         for (int v = 0; v < want; ++v) {
-            const uint32_t rb = (uint32_t)((__ballot(is_ins && rank == nfree + v) >> gshift) & 0xFFFFu);
+            const uint32_t rb = (uint32_t)((__ballot(is_ins && q == nfree + v) >> gshift) & 0xFFFFu);
             const int rl = __ffs(rb) - 1;
             const uint64_t s_in = __shfl(e.score, rl, GA);
             // smallest resident by (score, key) among the slots not yet taken; the lane's keys are
@@ -477,13 +526,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             for (int q2 = 0; q2 < SPL / 2; ++q2) {
                 const ulonglong2 kk = kp2[q2];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int q = 2 * q2 + h;
-                    const uint64_t kq = h ? kk.y : kk.x;
-                    const bool better = (((taken >> q) & 1u) == 0u) & ((sc[q] < ls) | ((sc[q] == ls) & (kq < lk)));
-                    ls = better ? sc[q] : ls;
-                    lk = better ? kq : lk;
-                    lslot = better ? lane * SPL + q : lslot;
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int z = 2 * q2 + hh;
+                    const uint64_t kz = hh ? kk.y : kk.x;
+                    const bool better = (((taken >> z) & 1u) == 0u) & ((sc[z] < ls) | ((sc[z] == ls) & (kz < lk)));
+                    ls = better ? sc[z] : ls;
+                    lk = better ? kz : lk;
+                    lslot = better ? lane * SPL + z : lslot;
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -495,13 +544,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             const int vsl = __shfl(lslot, ol, GA);
             if (lane == ol) taken |= 1u << (vsl & 7);
             if (lane == rl) {
-                new_slot = vsl;
+                vslot = vsl;
                 vkey = gk;
                 vscore = gm;
                 evi = v;
                 evicts = true;
             }
             ++nev;
+        }
+        admitted = is_ins && (q < nfree || evicts);
+        if (is_direct && admitted) new_slot = e.slot;
+        if (want > 0) {
+            // Slots are not observable, so a direct insert keeps the free slot it took.  The
+            // listed inserts that rank among the first nfree take, in rank order, the slots given
+            // up by direct inserts (their own free slot when refused, the victim's slot when they
+            // evicted), also in rank order; a listed insert that evicts takes its victim's slot.
+            const bool gives = is_direct && (!admitted || evicts);
+            const bool needs = is_ins && !is_direct && q < nfree;
+            const uint32_t gm_ = (uint32_t)((__ballot(gives) >> gshift) & 0xFFFFu);
+            const uint32_t nm_ = (uint32_t)((__ballot(needs) >> gshift) & 0xFFFFu);
+            int gi = 0, ki = 0;
+            for (int x = 0; x < (int)m; ++x) {
+                const int qx = __shfl(q, x, GA);
+                gi += (int)(((gm_ >> x) & 1u) && qx < q);
+                ki += (int)(((nm_ >> x) & 1u) && qx < q);
+            }
+            if (gives) s_pool[g][gi] = (uint8_t)(admitted ? vslot : e.slot);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // the group is inside one wave: its LDS accesses stay in order
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (needs) new_slot = s_pool[g][ki];
+            if (is_ins && !is_direct && evicts) new_slot = vslot;
         }
     }
 
@@ -511,9 +584,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t tot = 0;
-            for (int q = 0; q < kApplyGroups; ++q) {
-                s_off[q] = tot;
-                tot += s_nev[q];
+            for (int z = 0; z < kApplyGroups; ++z) {
+                s_off[z] = tot;
+                tot += s_nev[z];
             }
             s_base = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(ev.count), (unsigned long long)tot) : 0ull;
         }
@@ -524,12 +597,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
 
     // statuses and evicted (key, score)
     if (is_upd) w.sstat[e.w >> 32] = 1;  // UPDATED
-    if (is_ins) w.sstat[e.w >> 32] = new_slot < 0 ? 4 : (evicts ? 3 : 2);
+    if (is_ins) w.sstat[e.w >> 32] = q < nfree ? 2 : (evicts ? 3 : 4);
     if (evicts && ev.keys) {
         ev.keys[ev_base + evi] = vkey;
         ev.scores[ev_base + evi] = vscore;
     }
-    // slot metadata, by the owning lane: updates first, then inserts
+    // slot metadata, by the owning lane: updates first, then admitted inserts (a direct insert's key
+    // and score are in place already)
     for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
         const int x = __ffs(ub) - 1;
         const int us = __shfl((int)e.slot, x, GA);
@@ -540,25 +614,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         const int x = __ffs(ib) - 1;
         const int ns = __shfl(new_slot, x, GA);
         if (ns < 0) continue;
+        const bool dir = __shfl((int)is_direct, x, GA) != 0;
         const uint64_t nk = __shfl(e.key, x, GA);
         const uint64_t nsc = __shfl(e.score, x, GA);
         const int nd = __shfl((int)e.dg, x, GA);
         if ((ns >> 3) == lane) {
-            t.keys[eb + ns] = nk;
-            t.scores[eb + ns] = nsc;
+            if (!dir) {
+                t.keys[eb + ns] = nk;
+                t.scores[eb + ns] = nsc;
+            }
             t.dig[eb + ns] = (uint8_t)nd;
             if (full_after) {
 #pragma unroll
-                for (int q = 0; q < SPL; ++q)
-                    if ((ns & 7) == q) {
-                        sc[q] = nsc;
-                        kc[q] = nk;
+                for (int z = 0; z < SPL; ++z)
+                    if ((ns & 7) == z) {
+                        sc[z] = nsc;
+                        kc[z] = nk;
                     }
             }
         }
     }
-    // rows: chunk c of every row by lane c mod 16; updates before evictions.  find_or_insert
-    // (w.out set) keeps a resident row and returns it; every insert returns its own row.
+    // rows: chunk c of every row by lane c mod 16; updates, then the victims' rows copied out, then
+    // the listed inserts.  find_or_insert (w.out set) keeps a resident row and returns it; every
+    // insert returns its own row.
     const uint32_t chunks = t.dim >> 2;
     for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
         const int x = __ffs(ub) - 1;
@@ -582,25 +660,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             for (uint32_t c = lane; c < chunks; c += GA) o[c] = src[c];
         }
     }
+    if (nev && ev.vals) {
+        for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
+            const int x = __ffs(ib) - 1;
+            if (!__shfl((int)evicts, x, GA)) continue;
+            const int vs = __shfl(vslot, x, GA);
+            const int xi = __shfl(evi, x, GA);
+            const uint4* src = reinterpret_cast<const uint4*>(t.row(eb + vs));
+            uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
+            for (uint32_t c = lane; c < chunks; c += GA) out[c] = src[c];
+        }
+    }
     for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
         const int x = __ffs(ib) - 1;
         const int ns = __shfl(new_slot, x, GA);
-        if (ns < 0) continue;
+        if (ns < 0 || __shfl((int)is_direct, x, GA)) continue;
         const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
-        const bool xe = __shfl((int)evicts, x, GA) != 0;
-        const int xi = __shfl(evi, x, GA);
         uint4* dst = reinterpret_cast<uint4*>(t.row(eb + ns));
         const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
-        if (xe && ev.vals) {
-            uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + xi) * t.dim);
-            for (uint32_t c = lane; c < chunks; c += GA) {
-                const uint4 old = dst[c];
-                out[c] = old;
-                dst[c] = src[c];
-            }
-        } else {
-            for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
-        }
+        for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
     }
     // cached minimum of a full bucket (exact; every slot is occupied now)
     if (full_after) {
@@ -610,12 +688,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         for (int q2 = 0; q2 < SPL / 2; ++q2) {
             const ulonglong2 kk = kp2[q2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = 2 * q2 + h;
-                const uint64_t kq = h ? kk.y : kk.x;
-                const bool better = (sc[q] < ls) | ((sc[q] == ls) & (kq < lk));
-                ls = better ? sc[q] : ls;
-                lk = better ? kq : lk;
+            for (int hh = 0; hh < 2; ++hh) {
+                const int z = 2 * q2 + hh;
+                const uint64_t kz = hh ? kk.y : kk.x;
+                const bool better = (sc[z] < ls) | ((sc[z] == ls) & (kz < lk));
+                ls = better ? sc[z] : ls;
+                lk = better ? kz : lk;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -632,10 +710,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
 // slow apply: one wave per bucket with more than 16 operations
 __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint64_t cs[192], ck[192], cw[192];  // insert candidates: score, key, w
+    __shared__ uint8_t cd[192];                     // and the free slot a direct insert took (0xFF: listed)
     __shared__ uint64_t ns_[128], nk_[128], nw_[128];
+    __shared__ uint8_t nd_[128];
     __shared__ uint64_t S_[128], K_[128];           // residents by slot (updates applied)
     __shared__ uint64_t rs[128], rk[128];           // smallest residents in (score, key) order
-    __shared__ uint8_t rslot[128], elist[128], dslot[128], uflag[128], nflag[128];
+    __shared__ uint8_t rslot[128], dslot[128], uflag[128], nflag[128], gave[128], plist[128];
     __shared__ uint64_t newk[128], news[128];
     __shared__ unsigned long long ev_base_s;
 
@@ -647,10 +727,10 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (uint32_t si = blockIdx.x; si < nslow; si += gridDim.x) {
         const uint32_t b = w.slow[si];
-        const uint32_t m = t.cnt[b];
+        const uint32_t m = routed_ops(t.cnt[b]);
         const size_t eb = (size_t)b * kSlots;
 
-        // residents
+        // residents: the slots occupied before the call (a direct insert's slot still has a zero digest)
         const bool o0 = t.dig[eb + lane] != 0;
         const bool o1 = t.dig[eb + lane + 64] != 0;
         S_[lane] = o0 ? t.scores[eb + lane] : ~0ull;
@@ -659,21 +739,19 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         K_[lane + 64] = o1 ? t.keys[eb + lane + 64] : ~0ull;
         uflag[lane] = uflag[lane + 64] = 0;
         nflag[lane] = nflag[lane + 64] = 0;
-        const uint64_t bal0 = __ballot(o0), bal1 = __ballot(o1);
-        const int occ = __popcll(bal0) + __popcll(bal1);
+        gave[lane] = gave[lane + 64] = 0;
+        const int occ = __popcll(__ballot(o0)) + __popcll(__ballot(o1));
         const int nfree = kSlots - occ;
-        if (!o0) elist[__popcll(~bal0 & below)] = (uint8_t)lane;
-        if (!o1) elist[__popcll(~bal0) + __popcll(~bal1 & below)] = (uint8_t)(lane + 64);
         __syncthreads();
 
         // stream the operations: updates applied at once, inserts reduced to the best 128
         int nbest = 0;
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const bool has = c0 + lane < m;
-            Entry e{0, 0, 0, kInsertSlot};
+            Entry e{0, 0, 0, 0, 0, kOpUpdate, 0};
             if (has) e = fetch_entry(w, b, c0 + lane);
-            const bool upd = has && e.slot != kInsertSlot;
-            const bool ins = has && e.slot == kInsertSlot;
+            const bool upd = has && e.kind == kOpUpdate;
+            const bool ins = has && e.kind != kOpUpdate;
             if (upd) {
                 S_[e.slot] = e.score;
                 uflag[e.slot] = 1;
@@ -694,8 +772,8 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             }
             const uint64_t ib = __ballot(ins);
             if (w.out) {  // find_or_insert: every insert returns its own row
-                for (uint64_t q = ib; q; q &= q - 1) {
-                    const int x = __ffsll((unsigned long long)q) - 1;
+                for (uint64_t z = ib; z; z &= z - 1) {
+                    const int x = __ffsll((unsigned long long)z) - 1;
                     const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x);
                     uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
                     const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
@@ -708,14 +786,15 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                 cs[at] = e.score;
                 ck[at] = e.key;
                 cw[at] = e.w;
+                cd[at] = e.kind == kOpDirect ? e.slot : (uint8_t)0xFF;
             }
             __syncthreads();
             const int tot = nbest + cn;
             int r[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int j = lane + 64 * q;
-                r[q] = -1;
+            for (int z = 0; z < 3; ++z) {
+                const int j = lane + 64 * z;
+                r[z] = -1;
                 if (j < tot) {
                     const uint64_t s = cs[j], k = ck[j];
                     int rr = 0;
@@ -723,20 +802,22 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                         const uint64_t sx = cs[x];
                         rr += (sx > s) || (sx == s && ck[x] < k);
                     }
-                    r[q] = rr;
+                    r[z] = rr;
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int j = lane + 64 * q;
+            for (int z = 0; z < 3; ++z) {
+                const int j = lane + 64 * z;
                 if (j < tot) {
-                    if (r[q] < 128) {
-                        ns_[r[q]] = cs[j];
-                        nk_[r[q]] = ck[j];
-                        nw_[r[q]] = cw[j];
+                    if (r[z] < 128) {
+                        ns_[r[z]] = cs[j];
+                        nk_[r[z]] = ck[j];
+                        nw_[r[z]] = cw[j];
+                        nd_[r[z]] = cd[j];
                     } else {
                         w.sstat[cw[j] >> 32] = 4;  // REJECTED: 128 better inserts target this bucket
+                        if (cd[j] != 0xFF) gave[cd[j]] = 1;  // a refused direct insert gives up its slot
                     }
                 }
             }
@@ -746,6 +827,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                 cs[j] = ns_[j];
                 ck[j] = nk_[j];
                 cw[j] = nw_[j];
+                cd[j] = nd_[j];
             }
             __syncthreads();
         }
@@ -754,9 +836,9 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         const int need = nbest - nfree;
         if (need > 0) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int sl = lane + 64 * q;
-                if (!(q ? o1 : o0)) continue;
+            for (int z = 0; z < 2; ++z) {
+                const int sl = lane + 64 * z;
+                if (!(z ? o1 : o0)) continue;
                 const uint64_t s = S_[sl], k = K_[sl];
                 int rr = 0;
                 for (int x = 0; x < kSlots; ++x) {
@@ -772,30 +854,57 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         }
         __syncthreads();
 
-        // decisions: insert j takes free slot j, or competes with the (j-nfree)-th smallest resident
+        // decisions: candidate j is inserted (j < nfree), or competes with the (j-nfree)-th
+        // smallest resident; a direct insert keeps the free slot it took and gives it up when
+        // refused, or gives up its victim's slot when it evicts; listed inserts take victims'
+        // slots, and the ones ranked below nfree take the given-up slots
         bool adm[2];
         uint8_t st[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int j = lane + 64 * q;
-            adm[q] = false;
-            st[q] = 0;
+        for (int z = 0; z < 2; ++z) {
+            const int j = lane + 64 * z;
+            adm[z] = false;
+            st[z] = 0;
             if (j < nbest) {
+                const bool dir = cd[j] != 0xFF;
+                dslot[j] = 0xFF;
                 if (j < nfree) {
-                    adm[q] = true;
-                    st[q] = 2;  // INSERTED
-                    dslot[j] = elist[j];
+                    adm[z] = true;
+                    st[z] = 2;  // INSERTED
+                    if (dir) dslot[j] = cd[j];
                 } else {
                     const int v = j - nfree;
                     if (v < occ && cs[j] > rs[v]) {
-                        adm[q] = true;
-                        st[q] = 3;  // INSERTED_EVICT
-                        dslot[j] = rslot[v];
+                        adm[z] = true;
+                        st[z] = 3;  // INSERTED_EVICT
+                        if (dir) {
+                            dslot[j] = cd[j];
+                            gave[rslot[v]] = 1;
+                        } else {
+                            dslot[j] = rslot[v];
+                        }
                     } else {
-                        st[q] = 4;  // REJECTED
+                        st[z] = 4;  // REJECTED
+                        if (dir) gave[cd[j]] = 1;
                     }
                 }
             }
+        }
+        __syncthreads();
+        // given-up slots in slot order, handed to the listed inserts ranked below nfree in rank order
+        {
+            const bool g0 = gave[lane] != 0, g1 = gave[lane + 64] != 0;
+            const uint64_t b0 = __ballot(g0), b1 = __ballot(g1);
+            if (g0) plist[__popcll(b0 & below)] = (uint8_t)lane;
+            if (g1) plist[__popcll(b0) + __popcll(b1 & below)] = (uint8_t)(lane + 64);
+        }
+        __syncthreads();
+        {
+            const bool w0 = lane < nbest && lane < nfree && cd[lane] == 0xFF;
+            const bool w1 = lane + 64 < nbest && lane + 64 < nfree && cd[lane + 64] == 0xFF;
+            const uint64_t b0 = __ballot(w0), b1 = __ballot(w1);
+            if (w0) dslot[lane] = plist[__popcll(b0 & below)];
+            if (w1) dslot[lane + 64] = plist[__popcll(b0) + __popcll(b1 & below)];
         }
         const int nadm = __popcll(__ballot(adm[0])) + __popcll(__ballot(adm[1]));
         const int nev = nadm > nfree ? nadm - nfree : 0;
@@ -805,12 +914,12 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         __syncthreads();
         const uint64_t ev_base = ev_base_s;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int j = lane + 64 * q;
+        for (int z = 0; z < 2; ++z) {
+            const int j = lane + 64 * z;
             if (j >= nbest) continue;
-            w.sstat[cw[j] >> 32] = st[q];
-            if (!adm[q]) continue;
-            if (st[q] == 3 && ev.keys) {
+            w.sstat[cw[j] >> 32] = st[z];
+            if (!adm[z]) continue;
+            if (st[z] == 3 && ev.keys) {
                 const uint64_t x = ev_base + (uint64_t)(j - nfree);
                 ev.keys[x] = rk[j - nfree];
                 ev.scores[x] = rs[j - nfree];
@@ -819,28 +928,27 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             newk[dslot[j]] = ck[j];
             news[dslot[j]] = cs[j];
         }
-        // rows of admitted inserts: chunk c by lane c mod 64; victims copied out first
+        // rows: chunk c by lane c mod 64; the victims' rows copied out first, then the listed inserts
+        if (ev.vals) {
+            for (int v = 0; v < nev; ++v) {
+                const uint4* src = reinterpret_cast<const uint4*>(t.row(eb + rslot[v]));
+                uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + (uint64_t)v) * t.dim);
+                for (uint32_t c = lane; c < chunks; c += 64) out[c] = src[c];
+            }
+        }
         for (int j = 0; j < nadm; ++j) {
+            if (cd[j] != 0xFF) continue;  // a direct insert's row is in place
             uint4* dst = reinterpret_cast<uint4*>(t.row(eb + dslot[j]));
             const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)(uint32_t)cw[j] * t.dim);
-            if (j >= nfree && ev.vals) {
-                uint4* out = reinterpret_cast<uint4*>(ev.vals + (ev_base + (uint64_t)(j - nfree)) * t.dim);
-                for (uint32_t c = lane; c < chunks; c += 64) {
-                    const uint4 old = dst[c];
-                    out[c] = old;
-                    dst[c] = src[c];
-                }
-            } else {
-                for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
-            }
+            for (uint32_t c = lane; c < chunks; c += 64) dst[c] = src[c];
         }
         __syncthreads();
         // slot metadata by the owning lane; the minimum of the full bucket
         uint64_t lm = ~0ull, lk = ~0ull;
         const bool full = nadm >= nfree;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int sl = lane + 64 * q;
+        for (int z = 0; z < 2; ++z) {
+            const int sl = lane + 64 * z;
             if (nflag[sl]) {
                 t.keys[eb + sl] = newk[sl];
                 t.scores[eb + sl] = news[sl];
@@ -891,12 +999,12 @@ __global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t*
 }
 
 template <int G>
-static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const uint64_t* scores,
-                         hipStream_t s, uint64_t* ev_count = nullptr) {
+static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
+                         const uint64_t* scores, hipStream_t s, uint64_t* ev_count = nullptr) {
     if (w.fused)
-        k_route<G, true><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, ev_count);
+        k_route<G, true><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores, ev_count);
     else
-        k_route<G, false><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, scores, nullptr);
+        k_route<G, false><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores, nullptr);
 }
 
 hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
@@ -909,12 +1017,12 @@ hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n,
 }
 
 hipError_t launch_upsert_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
-                               const uint64_t* scores, int group, hipStream_t s) {
+                               const float* vals, const uint64_t* scores, int group, hipStream_t s) {
     if (n == 0) return hipSuccess;
     switch (group) {
-        case 4: launch_route<4>(t, w, n, keys, scores, s); break;
-        case 16: launch_route<16>(t, w, n, keys, scores, s); break;
-        default: launch_route<8>(t, w, n, keys, scores, s); break;
+        case 4: launch_route<4>(t, w, n, keys, vals, scores, s); break;
+        case 16: launch_route<16>(t, w, n, keys, vals, scores, s); break;
+        default: launch_route<8>(t, w, n, keys, vals, scores, s); break;
     }
     return hipGetLastError();
 }
@@ -951,7 +1059,7 @@ hipError_t launch_upsert_rounds(const TableView& t, const UpsertWs& w, uint64_t 
             if ((e = launch_fill_zero(w.okey, w.P * 8, s)) != hipSuccess) break;
             if ((e = launch_fill_zero(w.ctr + kCtrSlow, 2 * sizeof(uint32_t), s)) != hipSuccess) break;
         }
-        if ((e = launch_upsert_route(t, wr, n, keys, scores, group, s)) != hipSuccess) break;
+        if ((e = launch_upsert_route(t, wr, n, keys, vals, scores, group, s)) != hipSuccess) break;
         e = launch_upsert_apply(t, wr, n, vals, ev, s);
     }
     return e;
@@ -971,12 +1079,12 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
         wf.fused = 1;
         wf.in_scores = scores;
         switch (group) {
-            case 4: launch_route<4>(t, wf, n, keys, scores, s, ev.count); break;
-            case 16: launch_route<16>(t, wf, n, keys, scores, s, ev.count); break;
-            default: launch_route<8>(t, wf, n, keys, scores, s, ev.count); break;
+            case 4: launch_route<4>(t, wf, n, keys, vals, scores, s, ev.count); break;
+            case 16: launch_route<16>(t, wf, n, keys, vals, scores, s, ev.count); break;
+            default: launch_route<8>(t, wf, n, keys, vals, scores, s, ev.count); break;
         }
         const uint64_t fb = (t.nbuckets + 255) / 256;
-        k_fixup<<<(unsigned)(fb < 256 ? fb : 256), 256, 0, s>>>(t, wf);
+        k_fixup<<<(unsigned)(fb < 256 ? fb : 256), 256, 0, s>>>(t, wf, vals);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_upsert_apply(t, wf, n, vals, ev, s)) != hipSuccess) return e;
     }

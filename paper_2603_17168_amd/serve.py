@@ -52,9 +52,11 @@ class Trace:
     ops: int array (REQ_*), sizes: int array, keys: int64 device tensor of sum(sizes) keys,
     values: float32 [sum(insert sizes), dim] device tensor for the inserts (in request order),
     arrivals: float seconds.  with_results allocates per-request result buffers (for checks);
-    otherwise outputs live in the server's recycled arena."""
+    otherwise outputs live in the server's recycled arena.  shared_values: `values` holds the rows
+    of the largest insert only, and every insert reads its rows from its start (timing runs)."""
 
-    def __init__(self, table: cskv.Table, ops, sizes, keys, values, arrivals, with_results=False):
+    def __init__(self, table: cskv.Table, ops, sizes, keys, values, arrivals, with_results=False,
+                 shared_values=False):
         self.table = table
         self.ops = np.asarray(ops, dtype=np.int64)
         self.sizes = np.asarray(sizes, dtype=np.int64)
@@ -66,6 +68,10 @@ class Trace:
         self.key_off = np.concatenate([[0], np.cumsum(self.sizes)])
         ins = self.ops == REQ_INSERT_AND_EVICT
         self.val_off = np.concatenate([[0], np.cumsum(np.where(ins, self.sizes, 0))])
+        if shared_values:  # every insert reads its rows from the start of `values` (timing runs)
+            if with_results:
+                raise ValueError("shared_values is for timing runs: its inserts share result offsets")
+            self.val_off = np.zeros_like(self.val_off)
         nf = int(self.sizes[~ins].sum())
         ni = int(self.sizes[ins].sum())
         if with_results:

@@ -34,8 +34,9 @@ def test_table_bytes():
     lib = cskv.lib()
     nb, dim = 2048, 8
     got = lib.cskv_table_bytes(nb * 128, 128, dim)
-    # digests + keys + scores + rows per slot, plus 20 bytes per bucket (each array 256-aligned)
-    expect = nb * 128 * (1 + 8 + 8 + 4 * dim) + nb * 20
+    # digests + keys + scores + rows per slot, plus 24 bytes per bucket (operation counts and the
+    # cached minimum; each array 256-aligned)
+    expect = nb * 128 * (1 + 8 + 8 + 4 * dim) + nb * 24
     assert expect <= got <= expect + 6 * 256
     assert lib.cskv_table_bytes(0, 128, 8) == 0
     assert lib.cskv_table_bytes(128 * 6, 128, 8) == 0  # 6 buckets

@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -42,11 +43,14 @@ def test_upsert_byte_models():
     evict = insert + 2 * 8 * 128 + 64
     mixed = bench.upsert_bytes_contract(32, 0.5, {cskv.ST_INSERTED: 1, cskv.ST_INSERTED_EVICT: 3})
     assert mixed == pytest.approx((insert + 3 * evict) / 4)
-    # the free-slot model: below load 1 no score line is read
-    assert bench.upsert_bytes_per_key(32, 0.9, 1 << 20, 1 << 19) == 8 + V + 2 * 128 + 17 + V + 1
-    # at load 1 each bucket's score line (8 lines) is read once per call, shared by its inserts
-    full = bench.upsert_bytes_per_key(32, 1.0, 1 << 20, 1 << 19)
-    assert full == pytest.approx(8 + V + 2 * 128 + 17 + V + 1 + 8 * 128 * 0.5)
+    # the priced model: phase D2 reads the candidates' minima (a granule each) per key, and the
+    # score and key lines (16 lines) once per touched bucket, shared by that bucket's keys
+    assert bench.upsert_bytes_model(32, 0.5, {cskv.ST_INSERTED: 7}, 1 << 20, 1 << 19) == pytest.approx(insert)
+    share = 16 * 128 * (1 << 19) * (1 - np.exp(-2.0)) / (1 << 20)
+    assert bench.upsert_bytes_model(32, 1.0, {cskv.ST_INSERTED_EVICT: 5}, 1 << 20, 1 << 19) == pytest.approx(
+        8 + V + 2 * 128 + 64 + 3 * 64 + V + 1 + 3 * 64 + share)
+    assert bench.upsert_bytes_model(32, 1.0, {cskv.ST_REJECTED: 5}, 1 << 20, 1 << 19) == pytest.approx(
+        8 + 2 * 128 + 2 * 64 + 64 + 1 + share)
 
 
 def test_traffic_records_follow_their_sources(monkeypatch):
