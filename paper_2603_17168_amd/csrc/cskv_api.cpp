@@ -55,9 +55,11 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds) {
     L.off_zero_end = o;
     L.off_inc = o;     o = align256(o + P * 8);
     L.off_sat = o;     o = align256(o + P * 4);
+    L.off_minc = o;    o = align256(o + P * 8);
     L.off_zero_end_lfu = o;
     L.off_sstat = o;   o = align256(o + P);
     L.off_slot_of = o; o = align256(o + n * 4);
+    L.off_rinc = o;    o = align256(o + n * 8);
     L.off_il = o;      o = align256(o + nl * sizeof(OpEntry));
     L.off_ol = o;      o = align256(o + P * sizeof(OpEntry));
     L.off_slow = o;    o = align256(o + nslow * 4);
@@ -259,6 +261,8 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     w.sat = reinterpret_cast<uint32_t*>(b + L.off_sat);
     w.sstat = b + L.off_sstat;
     w.slot_of = reinterpret_cast<uint32_t*>(b + L.off_slot_of);
+    w.rinc = reinterpret_cast<uint64_t*>(b + L.off_rinc);
+    w.minc = reinterpret_cast<uint64_t*>(b + L.off_minc);
     w.il = reinterpret_cast<OpEntry*>(b + L.off_il);
     w.ol = reinterpret_cast<OpEntry*>(b + L.off_ol);
     w.slow = reinterpret_cast<uint32_t*>(b + L.off_slow);

@@ -13,9 +13,11 @@
 //
 //   upsert workspace (n keys, P = power of two >= 2n, C = per-bucket inline capacity):
 //     zeroed on entry: dd {key u64, last u32, claim u32}[P], okey u64[P], ctr u32[64],
-//                      and for LFU inc u64[P], sat u32[P]
+//                      and for LFU inc u64[P], sat u32[P], minc u64[P]
 //     sstat u8[P]                      status of each distinct key's operation
-//     slot_of u32[n]                   dedupe slot of input i (or kNoSlot)
+//     slot_of u32[n]                   dedupe slot of input i, or (block-local dedupe) the position of
+//                                      its block representative (kNoSlot: reserved key)
+//     rinc u64[n]                      block-local dedupe, LFU: representatives' increment sums
 //     il OpEntry[B*C]                  per-bucket operation lists: key, new score,
 //                                      (dedupe slot << 32 | input position), and a meta word (slot,
 //                                      digest, kind, free slots of the bucket before the call)
@@ -101,9 +103,12 @@ struct UpsertWs {
     float* out;      // find_or_insert: rows returned per occurrence (resident rows are kept); else null
     int rounds;      // route sub-rounds of the call (1: the whole batch routes at once)
     int round;       // the sub-round a route / apply launch serves
-    int fused = 0;   // routing claimed the dedupe entries itself (first occurrences route; the
-                     // apply takes the last occurrence's position and score from the set)
-    const uint64_t* in_scores = nullptr;  // the call's scores (CUSTOM scores or LFU increments), for that fix-up
+    int local = 0;   // block-local dedupe: slot_of[i] is the position of the occurrence that represents
+                     // key i in its block of the input (its last occurrence there), statuses are kept per
+                     // representative position, and a key repeated across blocks has one list entry
+                     // per block, merged by the apply pass
+    uint64_t* rinc;  // local dedupe, LFU: a representative's block sum of increments (saturated = ~0)
+    uint64_t* minc;  // LFU: per dedupe-set slot, the sum of the merged entries' increments (slow apply)
 };
 
 // one batch of a merged run of finds (reader group): keys [begin, begin + n) of the run
@@ -136,8 +141,8 @@ struct StorageLayout {
 };
 
 struct UpsertLayout {
-    size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_zero_end, off_zero_end_lfu;
-    size_t off_sstat, off_slot_of, off_il, off_ol, off_slow, off_touched, off_rank, off_bsum, total;
+    size_t off_dd, off_okey, off_ctr, off_inc, off_sat, off_minc, off_zero_end, off_zero_end_lfu;
+    size_t off_sstat, off_slot_of, off_rinc, off_il, off_ol, off_slow, off_touched, off_rank, off_bsum, total;
     uint64_t P;
     int logP;
     uint32_t cap;

@@ -2,11 +2,12 @@
 // CDNA4 (gfx950, wave64): Alg. 2 (in-line upsert with admission control and eviction) inside
 // Alg. 3 (score-based dual-bucket choice), under the deterministic batch order of cskv.h.
 //
-// One call is a fixed sequence on one stream:
+// A plain call (one route round) is a fixed sequence on one stream:
 //   zero     one fill of the call's scratch (dedupe set, overflow keys, counters)
-//   dedupe   one set entry per distinct key (one CAS per distinct key; atomicMax only for
-//            repeats): last occurrence, LFU increment sum
-//   route    G lanes per distinct key, against the table as it was before the call: update slot
+//   dedupe   block-local, in LDS: each block of 1024 input positions keeps one representative per
+//            key, its last occurrence in the block (and, for LFU, the block's sum of the key's
+//            increments); no global atomic per key
+//   route    G lanes per representative, against the table as it was before the call: update slot
 //            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
 //            smaller cached bucket minimum (score, key)).  One atomic on the target's counter
 //            (inserts in the low half, updates in the high half) gives the operation its place
@@ -15,21 +16,24 @@
 //            insert writes its key, score and row at once into the r-th of those free slots
 //            (a direct insert).  Digest bytes are not written here, so every key of the call
 //            sees the digest lines, occupancies and free-slot order of the table before it.
-//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block.  A bucket that
-//            received only inserts, no more than its free slots, just has the digest bytes of
-//            its direct inserts written.  Otherwise: updates, then inserts ranked by (score desc,
-//            key asc): the first ones (as many as there were free slots) are inserted, the rest
-//            compete with the smallest residents by (score, key) - strict admission.  Slot
-//            positions are not observable, so a direct insert keeps the slot it took; the
-//            inserts still waiting in the list take the victims' slots and the free slots of
-//            direct inserts that were refused or that evicted; victims are copied out first
-//   slow     one wave per bucket that received more than 16 operations: same rules, with the
-//            best 128 inserts kept in LDS
-//   finish   per-occurrence status
-// A plain call of one route round fuses dedupe and route (the first occurrence of a key claims
-// its set entry and routes it; k_fixup then hands each operation its last occurrence's position
-// and score when some key repeated, and rewrites a direct insert's score and row); phased
-// programs and route sub-rounds keep the separate passes.
+//            Routing depends only on the key and that table, so the representatives of a key
+//            repeated across blocks all land in the same bucket's list.
+//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block.  The entries of
+//            one key are merged first: the one with the largest input position (the key's last
+//            occurrence) wins, LFU increments are summed.  A bucket that received only inserts,
+//            no more than its free slots, just has the digest bytes of its direct inserts written.
+//            Otherwise: updates, then inserts ranked by (score desc, key asc): the first ones (as
+//            many as there were free slots) are inserted, the rest compete with the smallest
+//            residents by (score, key) - strict admission.  Slot positions are not observable,
+//            so a direct insert keeps the slot it took; the inserts still waiting in the list
+//            take the victims' slots and the free slots given up by merged or refused direct
+//            inserts and by direct inserts that evicted; victims are copied out first
+//   slow     one wave per bucket that received more than 16 operations: the same rules, with the
+//            entries of a key merged through the call's dedupe set and the best 128 inserts kept
+//            in LDS
+//   finish   per-occurrence status (from its representative)
+// Route sub-rounds and the phased (overlapped) programs dedupe the whole call first through a
+// global set (one CAS per occurrence, k_dedupe) and route only each key's last occurrence.
 // Every write to a table slot's key/score/digest in the apply kernels is made by the lane that
 // owns the slot, and every 16-byte chunk c of a row by lane c mod (lanes), so writes that must
 // follow one another (an update, then the eviction of the same entry) are ordered by program
@@ -68,9 +72,10 @@ __device__ __forceinline__ uint64_t scratch_hash(uint64_t x, int logP) { return 
 
 __device__ __forceinline__ uint64_t overflow_key(uint32_t b, uint32_t r) { return ((uint64_t)b << 32) + r + 1; }
 
-
 struct Entry {
-    uint64_t key, score, w;  // w = dedupe slot << 32 | input position
+    uint64_t key;
+    uint64_t score;          // CUSTOM / LRU: the operation's score; LFU: its increment (sum)
+    uint64_t w;              // dedupe slot (or representative position) << 32 | input position
     uint8_t slot;            // update: the resident slot; direct insert: the free slot it took
     uint8_t dg;              // the key's digest, computed once by routing
     uint8_t kind;            // OpKind
@@ -107,55 +112,93 @@ __device__ __forceinline__ Entry fetch_entry(const UpsertWs& w, uint32_t b, uint
     return load_entry(w.ol + q);
 }
 
-// where the r-th operation routed to bucket b is stored
-__device__ __forceinline__ OpEntry* entry_ptr(const UpsertWs& w, uint32_t b, uint32_t r) {
-    if (r < w.cap) return w.il + (size_t)b * w.cap + r;
-    const uint64_t ok = overflow_key(b, r);
-    uint64_t q = scratch_hash(ok, w.logP);
-    for (uint64_t probes = 0; probes < w.P && w.okey[q] != ok; ++probes) q = (q + 1) & (w.P - 1);
-    return w.ol + q;
-}
-
 // operations routed to a bucket by the running call (inserts + updates)
 __device__ __forceinline__ uint32_t routed_ops(uint64_t c) { return (uint32_t)c + (uint32_t)(c >> 32); }
 
-// After a fused routing pass in a call that repeated a key (else it returns at once): every
-// operation takes its key's last occurrence's position and score (CUSTOM: that occurrence's
-// score; LFU: the saturated sum of the increments, added to the resident score for an update),
-// and a direct insert's slot gets that score and the last occurrence's row (routing wrote the
-// claiming occurrence's).  A grid-stride loop over the buckets on a small grid, so that the
-// common case (no repeats) costs little more than one flag read.
-__global__ void __launch_bounds__(256) k_fixup(TableView t, UpsertWs w, const float* __restrict__ vals) {
-    if (w.ctr[kCtrDup] == 0) return;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint32_t chunks = t.dim >> 2;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < t.nbuckets; b += stride) {
-        const uint32_t m = routed_ops(t.cnt[b]);
-        for (uint32_t r = 0; r < m; ++r) {
-            OpEntry* op = entry_ptr(w, (uint32_t)b, r);
-            const Entry e = load_entry(op);
-            const uint32_t p = (uint32_t)(e.w >> 32);
-            const DedupeEntry de = w.dd[p];
-            const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
-            uint64_t score = e.score;
-            if (t.policy == 0) {
-                score = w.in_scores[last];
-            } else if (t.policy == 2) {
-                const uint64_t inc = w.sat[p] ? ~0ull : w.inc[p];
-                score = e.kind == kOpUpdate ? sat_add(t.scores[b * kSlots + e.slot], inc) : inc;
-            }
-            store_entry(op, e.key, score, ((uint64_t)p << 32) | last, e.slot, e.dg, e.kind, e.nfree);
-            if (e.kind == kOpDirect) {
-                const size_t ent = b * kSlots + e.slot;
-                t.scores[ent] = score;
-                if (last != (uint32_t)e.w) {
-                    uint4* dst = reinterpret_cast<uint4*>(t.row(ent));
-                    const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)last * t.dim);
-                    for (uint32_t c = 0; c < chunks; ++c) dst[c] = src[c];
-                }
-            }
+// the dedupe-set slot of key k: claims a free slot for a new key (CAS), else finds the key's slot
+__device__ __forceinline__ uint64_t set_slot(const UpsertWs& w, uint64_t k) {
+    const uint64_t mask = w.P - 1;
+    uint64_t x = scratch_hash(k, w.logP);
+    for (uint64_t probes = 0; probes < w.P; ++probes) {
+        const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[x].key), 0ull,
+                                                 (unsigned long long)k);
+        if (old == 0ull || old == k) break;
+        x = (x + 1) & mask;
+    }
+    return x;
+}
+
+// ------------------------------------------------------------------------------------------
+// block-local dedupe: 1024 input positions per 256-thread block, an LDS hash table of 2048 keys.
+// Each occurrence records the position of its key's last occurrence in the block (its
+// representative); a representative gets the block's (saturating) LFU sum of the key's increments.
+constexpr int kLocalKeys = 1024;
+constexpr int kLocalHash = 2048;
+
+template <bool LFU>
+__global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
+                                                      const uint64_t* __restrict__ scores, uint64_t* ev_count) {
+    __shared__ unsigned long long hk[kLocalHash];
+    __shared__ uint32_t hl[kLocalHash];
+    __shared__ unsigned long long hi[LFU ? kLocalHash : 1];
+    __shared__ uint32_t hs[LFU ? kLocalHash : 1];
+    __shared__ int repeated;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < kLocalHash; j += 256) {
+        hk[j] = 0ull;
+        hl[j] = 0u;
+        if constexpr (LFU) {
+            hi[j] = 0ull;
+            hs[j] = 0u;
         }
     }
+    if (tid == 0) repeated = 0;
+    if (blockIdx.x == 0 && tid == 0 && ev_count) *ev_count = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kLocalKeys;
+    constexpr int PER = kLocalKeys / 256;
+    int hslot[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t li = (uint32_t)(q * 256 + tid);
+        const uint64_t i = base + li;
+        hslot[q] = -1;
+        if (i >= n) continue;
+        const uint64_t k = keys[i];
+        if (reserved_key(k)) continue;
+        uint32_t h = (uint32_t)((fmix64(k) * kGold) >> (64 - 11));
+        for (int probes = 0; probes < kLocalHash; ++probes) {
+            const unsigned long long old = atomicCAS(&hk[h], 0ull, (unsigned long long)k);
+            if (old == 0ull) break;
+            if (old == k) {
+                repeated = 1;
+                break;
+            }
+            h = (h + 1) & (kLocalHash - 1);
+        }
+        hslot[q] = (int)h;
+        atomicMax(&hl[h], li + 1);
+        if constexpr (LFU) {
+            const unsigned long long inc = scores ? scores[i] : 1ull;
+            const unsigned long long old = atomicAdd(&hi[h], inc);
+            if (old + inc < old) atomicOr(&hs[h], 1u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint64_t i = base + (uint32_t)(q * 256 + tid);
+        if (i >= n) continue;
+        if (hslot[q] < 0) {
+            w.slot_of[i] = kNoSlot;
+            continue;
+        }
+        const uint64_t rep = base + hl[hslot[q]] - 1;
+        w.slot_of[i] = (uint32_t)rep;
+        if constexpr (LFU)
+            if (rep == i) w.rinc[i] = hs[hslot[q]] ? ~0ull : hi[hslot[q]];
+    }
+    if (tid == 0 && repeated) w.ctr[kCtrDup] = 1;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -255,23 +298,21 @@ __global__ void __launch_bounds__(256) k_rank_write(UpsertWs w, uint64_t n) {
 }
 
 // ------------------------------------------------------------------------------------------
-// FUSED: the routing kernel also claims the dedupe entries (one CAS per occurrence, by the
-// group's lane 0, issued after the digest loads); the claiming occurrence routes the key with its
-// own position and score (routing depends only on the key and the table before the call), later
-// occurrences only record themselves, and k_fixup replaces position, score (and a direct
-// insert's row) by the last occurrence's when the call repeated a key.  Otherwise the dedupe
-// pass ran before, and only each key's last occurrence routes.
-template <int G, bool FUSED>
+// LOCAL: the block-local dedupe ran before; each representative routes (its block's last
+// occurrence of the key, with the block's LFU sum).  Otherwise the global dedupe pass ran before
+// (sub-rounds, phased programs), and only each key's last occurrence routes.
+template <int G, bool LOCAL>
 __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                               const float* __restrict__ vals, const uint64_t* __restrict__ scores,
-                                               uint64_t* ev_count) {
+                                               const float* __restrict__ vals, const uint64_t* __restrict__ scores) {
     const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int lane = glane<G>();
-    if (FUSED && i == 0 && lane == 0 && ev_count) *ev_count = 0;
     if (i >= n) return;
     uint32_t p;
     bool dups = false;
-    if constexpr (!FUSED) {
+    if constexpr (LOCAL) {
+        if (w.slot_of[i] != (uint32_t)i) return;  // not its block's representative of the key
+        p = (uint32_t)i;
+    } else {
         p = w.slot_of[i];
         if (p == kNoSlot) return;
         dups = w.ctr[kCtrDup] != 0;  // else every occurrence is its key's last and only one
@@ -279,53 +320,22 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
             const DedupeEntry de = w.dd[p];
             if ((de.claim > de.last ? de.claim : de.last) != (uint32_t)(i + 1)) return;  // not the last occurrence
         }
-    }
-    if (w.rounds > 1) {  // only the keys of this sub-round's chunk
-        const uint64_t nd = w.ctr[kCtrDistinct];
-        if ((uint64_t)w.rank[i] * (uint64_t)w.rounds / nd != (uint64_t)w.round) return;
+        if (w.rounds > 1) {  // only the keys of this sub-round's chunk
+            const uint64_t nd = w.ctr[kCtrDistinct];
+            if ((uint64_t)w.rank[i] * (uint64_t)w.rounds / nd != (uint64_t)w.round) return;
+        }
     }
     const uint64_t k = keys[i];
     const uint64_t clock = *t.clock + 1;  // LRU: this call's clock (advanced after routing)
     const KeyHash h = hash_key(t, k);
     const bool two = h.b2 != h.b1;
     LineSeg<G> s1, s2;
-    if (FUSED && reserved_key(k)) {
-        if (lane == 0) w.slot_of[i] = kNoSlot;
-        return;
-    }
     s1.load(t.dig + (size_t)h.b1 * kSlots, lane);
     if (two) s2.load(t.dig + (size_t)h.b2 * kSlots, lane);  // an insert needs both occupancies
-    if constexpr (FUSED) {
-        int claimed = 0;
-        uint32_t q = 0;
-        if (lane == 0) {
-            const uint64_t mask = w.P - 1;
-            uint64_t x = scratch_hash(k, w.logP);
-            for (uint64_t probes = 0; probes < w.P; ++probes) {
-                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&w.dd[x].key), 0ull,
-                                                         (unsigned long long)k);
-                if (old == 0ull) {
-                    w.dd[x].claim = (uint32_t)(i + 1);
-                    claimed = 1;
-                    break;
-                }
-                if (old == k) {
-                    atomicMax(&w.dd[x].last, (uint32_t)(i + 1));
-                    w.ctr[kCtrDup] = 1;
-                    break;
-                }
-                x = (x + 1) & mask;
-            }
-            q = (uint32_t)x;
-            w.slot_of[i] = q;
-            if (t.policy == 2) {  // LFU: saturating sum of the increments
-                const uint64_t inc = scores ? scores[i] : 1ull;
-                const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.inc + x), (unsigned long long)inc);
-                if (old + inc < old) atomicOr(w.sat + x, 1u);
-            }
-        }
-        p = (uint32_t)__shfl((int)q, 0, G);
-        if (!__shfl(claimed, 0, G)) return;
+    uint64_t inc = 0;  // LFU: the increment this operation carries
+    if (t.policy == 2) {
+        if constexpr (LOCAL) inc = w.rinc[i];
+        else inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);
     }
     int slot = verify<G>(t, h.b1, s1.match(h.dg), k, lane);
     uint32_t tgt = h.b1;
@@ -333,17 +343,13 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
         slot = verify<G>(t, h.b2, s2.match(h.dg), k, lane);
         tgt = h.b2;
     }
-    uint64_t inc = 0;
-    if (t.policy == 2) inc = dups ? (w.sat[p] ? ~0ull : w.inc[p]) : (scores ? scores[i] : 1ull);  // FUSED: provisional
-    uint64_t ns;
-    const bool upd = slot >= 0;
-    uint32_t em = 0;  // inserts: this lane's share of the target's free slots (before the call)
+    // the operation's score: CUSTOM the caller's, LRU the call's clock, LFU the increment (the
+    // apply adds it to a resident's score)
+    const uint64_t ns = t.policy == 0 ? scores[i] : (t.policy == 1 ? clock : inc);
+    const bool upd = slot >= 0;  // UPDATE in place (Alg. 2, found)
+    uint32_t em = 0;             // inserts: this lane's share of the target's free slots (before the call)
     int nfree = 0;
-    if (upd) {  // UPDATE in place (Alg. 2, found)
-        if (t.policy == 0) ns = scores[i];
-        else if (t.policy == 1) ns = clock;
-        else ns = sat_add(t.scores[(size_t)tgt * kSlots + slot], inc);
-    } else {  // INSERT: candidate choice (Alg. 3)
+    if (!upd) {  // INSERT: candidate choice (Alg. 3)
         tgt = h.b1;
         const uint32_t em1 = s1.empty_mask();
         em = em1;
@@ -368,9 +374,6 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
             }
         }
         nfree = gsum_i<G>(__popc(em));
-        if (t.policy == 0) ns = scores[i];
-        else if (t.policy == 1) ns = clock;
-        else ns = inc;
     }
     unsigned long long old = 0;
     if (lane == 0) {
@@ -453,8 +456,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     // state carried over the block barrier
     Entry e{0, 0, 0, 0, 0, kOpUpdate, 0};
     bool is_upd = false, is_ins = false, is_direct = false, admitted = false, evicts = false;
-    int q = 0;          // rank of an insert among the bucket's inserts, (score desc, key asc)
-    int new_slot = -1;  // slot of an admitted insert (a direct insert keeps its own)
+    bool merged = false;  // an entry of a key whose later occurrence another entry carries
+    int win = 0;          // the lane holding this key's winning entry
+    int q = 0;            // rank of an insert among the bucket's inserts, (score desc, key asc)
+    int new_slot = -1;    // slot of an admitted insert (a direct insert keeps its own)
     int vslot = -1, evi = 0;
     uint64_t vkey = 0, vscore = 0;
     uint32_t upd_bits = 0, ins_bits = 0;
@@ -469,13 +474,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     if (m > 0) {
         const bool has = lane < (int)m;
         if (has) e = fetch_entry(w, b, (uint32_t)lane);
-        is_upd = has && e.kind == kOpUpdate;
-        is_ins = has && e.kind != kOpUpdate;
-        is_direct = has && e.kind == kOpDirect;
+        // merge the entries of one key (representatives of blocks that both held it): the largest
+        // input position wins, LFU increments add up
+        const uint32_t pos = (uint32_t)e.w;
+        uint32_t best = pos;
+        win = lane;
+        uint64_t incsum = e.score;
+        for (int x = 0; x < (int)m; ++x) {
+            const uint64_t kx = __shfl(e.key, x, GA);
+            const uint32_t px = (uint32_t)__shfl((int)pos, x, GA);
+            const uint64_t sx = __shfl(e.score, x, GA);
+            if (has && x != lane && kx == e.key) {
+                incsum = sat_add(incsum, sx);
+                if (px > best) {
+                    best = px;
+                    win = x;
+                }
+            }
+        }
+        merged = has && win != lane;
+        const bool live = has && !merged;
+        if (live && t.policy == 2) e.score = incsum;  // LFU: the key's whole increment
+        is_upd = live && e.kind == kOpUpdate;
+        is_ins = live && e.kind != kOpUpdate;
+        is_direct = live && e.kind == kOpDirect;
+        if (is_upd && t.policy == 2) e.score = sat_add(t.scores[eb + e.slot], e.score);
         upd_bits = (uint32_t)((__ballot(is_upd) >> gshift) & 0xFFFFu);
         ins_bits = (uint32_t)((__ballot(is_ins) >> gshift) & 0xFFFFu);
+        const int nins = __popc(ins_bits);
+        const bool any_merged = ((__ballot(merged) >> gshift) & 0xFFFFu) != 0;
         // free slots before the call: carried by every insert, else read from the digest line
-        nfree = gmax_i<GA>(is_ins ? (int)e.nfree : -1);
+        nfree = gmax_i<GA>(has && e.kind != kOpUpdate ? (int)e.nfree : -1);
         const bool plain = nu == 0 && (int)ni <= nfree;  // only inserts, all of them direct
         uint32_t taken = 0;  // free slots before the call (now holding direct inserts) are never victims
         if (!plain) {
@@ -483,8 +512,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             taken = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);
             nfree = gsum_i<GA>(__popc(taken));
         }
-        full_after = (int)ni >= nfree;
-        const int want = (int)ni - nfree;  // inserts beyond the free slots: they compete for victims
+        full_after = nins >= nfree;
+        const int want = nins - nfree;  // inserts beyond the free slots: they compete for victims
         if (want > 0) {
             for (int x = 0; x < (int)m; ++x) {
                 const uint64_t sx = __shfl(e.score, x, GA);
@@ -554,19 +583,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         }
         admitted = is_ins && (q < nfree || evicts);
         if (is_direct && admitted) new_slot = e.slot;
-        if (want > 0) {
+        if (want > 0 || any_merged) {
             // Slots are not observable, so a direct insert keeps the free slot it took.  The
-            // listed inserts that rank among the first nfree take, in rank order, the slots given
-            // up by direct inserts (their own free slot when refused, the victim's slot when they
-            // evicted), also in rank order; a listed insert that evicts takes its victim's slot.
-            const bool gives = is_direct && (!admitted || evicts);
+            // listed inserts that rank among the first nfree take, in rank order, the slots that
+            // direct entries give up (a merged or refused one its own free slot, an evicting one
+            // its victim's slot); a listed insert that evicts takes its victim's slot.  Slots
+            // given up and not taken stay free.
+            const bool dmerged = merged && e.kind == kOpDirect;
+            const bool gives = (is_direct && (!admitted || evicts)) || dmerged;
             const bool needs = is_ins && !is_direct && q < nfree;
+            const int gkey = dmerged ? 1024 + lane : q;  // order of the given-up slots
             const uint32_t gm_ = (uint32_t)((__ballot(gives) >> gshift) & 0xFFFFu);
             const uint32_t nm_ = (uint32_t)((__ballot(needs) >> gshift) & 0xFFFFu);
             int gi = 0, ki = 0;
             for (int x = 0; x < (int)m; ++x) {
                 const int qx = __shfl(q, x, GA);
-                gi += (int)(((gm_ >> x) & 1u) && qx < q);
+                const int gx = __shfl(gkey, x, GA);
+                gi += (int)(((gm_ >> x) & 1u) && gx < gkey);
                 ki += (int)(((nm_ >> x) & 1u) && qx < q);
             }
             if (gives) s_pool[g][gi] = (uint8_t)(admitted ? vslot : e.slot);
@@ -595,15 +628,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     if (m == 0) return;
     const uint64_t ev_base = ev.count ? s_base + s_off[g] : 0ull;
 
-    // statuses and evicted (key, score)
-    if (is_upd) w.sstat[e.w >> 32] = 1;  // UPDATED
-    if (is_ins) w.sstat[e.w >> 32] = q < nfree ? 2 : (evicts ? 3 : 4);
+    // statuses (a merged entry takes its key's) and evicted (key, score)
+    const int st = is_upd ? 1 : (is_ins ? (q < nfree ? 2 : (evicts ? 3 : 4)) : 0);
+    const int wst = __shfl(st, win, GA);
+    if ((int)lane < (int)m) w.sstat[e.w >> 32] = (uint8_t)wst;
     if (evicts && ev.keys) {
         ev.keys[ev_base + evi] = vkey;
         ev.scores[ev_base + evi] = vscore;
     }
     // slot metadata, by the owning lane: updates first, then admitted inserts (a direct insert's key
-    // and score are in place already)
+    // and score are in place already, its score only rewritten when merged entries added LFU
+    // increments)
     for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
         const int x = __ffs(ub) - 1;
         const int us = __shfl((int)e.slot, x, GA);
@@ -619,10 +654,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         const uint64_t nsc = __shfl(e.score, x, GA);
         const int nd = __shfl((int)e.dg, x, GA);
         if ((ns >> 3) == lane) {
-            if (!dir) {
-                t.keys[eb + ns] = nk;
-                t.scores[eb + ns] = nsc;
-            }
+            if (!dir) t.keys[eb + ns] = nk;
+            if (!dir || t.policy == 2) t.scores[eb + ns] = nsc;
             t.dig[eb + ns] = (uint8_t)nd;
             if (full_after) {
 #pragma unroll
@@ -634,29 +667,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             }
         }
     }
-    // rows: chunk c of every row by lane c mod 16; updates, then the victims' rows copied out, then
-    // the listed inserts.  find_or_insert (w.out set) keeps a resident row and returns it; every
-    // insert returns its own row.
+    // rows: chunk c of every row by lane c mod 16; updates (the winning entry's row), then the
+    // victims' rows copied out, then the listed inserts.  find_or_insert (w.out set) keeps a resident
+    // row and returns it for every entry of the key; every insert's entries return the key's row.
     const uint32_t chunks = t.dim >> 2;
     for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
         const int x = __ffs(ub) - 1;
         const int us = __shfl((int)e.slot, x, GA);
         const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
         uint4* dst = reinterpret_cast<uint4*>(t.row(eb + us));
-        if (w.out) {
-            uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
-            for (uint32_t c = lane; c < chunks; c += GA) o[c] = dst[c];
-        } else {
+        if (!w.out) {
             const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
             for (uint32_t c = lane; c < chunks; c += GA) dst[c] = src[c];
         }
     }
     if (w.out) {
-        for (uint32_t ib = ins_bits; ib; ib &= ib - 1) {
-            const int x = __ffs(ib) - 1;
+        for (int x = 0; x < (int)m; ++x) {
+            const int wx = __shfl(win, x, GA);
+            const bool uw = __shfl((int)is_upd, wx, GA) != 0;
             const uint32_t pos = (uint32_t)__shfl((int)(uint32_t)e.w, x, GA);
+            const uint32_t wpos = (uint32_t)__shfl((int)(uint32_t)e.w, wx, GA);
+            const int us = __shfl((int)e.slot, wx, GA);
             uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)pos * t.dim);
-            const uint4* src = reinterpret_cast<const uint4*>(vals + (size_t)pos * t.dim);
+            const uint4* src = uw ? reinterpret_cast<const uint4*>(t.row(eb + us))
+                                  : reinterpret_cast<const uint4*>(vals + (size_t)wpos * t.dim);
             for (uint32_t c = lane; c < chunks; c += GA) o[c] = src[c];
         }
     }
@@ -712,7 +746,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     __shared__ uint64_t cs[192], ck[192], cw[192];  // insert candidates: score, key, w
     __shared__ uint8_t cd[192];                     // and the free slot a direct insert took (0xFF: listed)
     __shared__ uint64_t ns_[128], nk_[128], nw_[128];
-    __shared__ uint8_t nd_[128];
+    __shared__ uint8_t nd_[128], cst[128];
     __shared__ uint64_t S_[128], K_[128];           // residents by slot (updates applied)
     __shared__ uint64_t rs[128], rk[128];           // smallest residents in (score, key) order
     __shared__ uint8_t rslot[128], dslot[128], uflag[128], nflag[128], gave[128], plist[128];
@@ -742,18 +776,45 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         gave[lane] = gave[lane + 64] = 0;
         const int occ = __popcll(__ballot(o0)) + __popcll(__ballot(o1));
         const int nfree = kSlots - occ;
+
+        // block-local dedupe leaves one entry per key and input block: merge a key's entries through
+        // the call's dedupe set (largest position + 1 in `last`, LFU increments summed in minc)
+        bool any_merged = false;
+        if (w.local) {
+            for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+                if (c0 + lane >= m) continue;
+                const Entry e = fetch_entry(w, b, c0 + lane);
+                const uint64_t x = set_slot(w, e.key);
+                atomicMax(&w.dd[x].last, (uint32_t)e.w + 1u);
+                if (t.policy == 2) {
+                    const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x),
+                                                             (unsigned long long)e.score);
+                    if (old + e.score < old) atomicOr(w.sat + x, 1u);
+                }
+            }
+            __threadfence();
+        }
         __syncthreads();
 
-        // stream the operations: updates applied at once, inserts reduced to the best 128
+        // stream the operations: a key's winning entry is applied (updates at once, inserts reduced
+        // to the best 128); an entry merged into another gives up the free slot it took, if any
         int nbest = 0;
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const bool has = c0 + lane < m;
             Entry e{0, 0, 0, 0, 0, kOpUpdate, 0};
             if (has) e = fetch_entry(w, b, c0 + lane);
-            const bool upd = has && e.kind == kOpUpdate;
-            const bool ins = has && e.kind != kOpUpdate;
+            bool live = has;
+            if (has && w.local) {
+                const uint64_t x = set_slot(w, e.key);
+                live = atomicOr(&w.dd[x].last, 0u) == (uint32_t)e.w + 1u;
+                if (live && t.policy == 2) e.score = atomicOr(w.sat + x, 0u) ? ~0ull : atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x), 0ull);
+                if (!live && e.kind == kOpDirect) gave[e.slot] = 1;
+            }
+            any_merged = any_merged || __ballot(has && !live) != 0;
+            const bool upd = live && e.kind == kOpUpdate;
+            const bool ins = live && e.kind != kOpUpdate;
             if (upd) {
-                S_[e.slot] = e.score;
+                S_[e.slot] = t.policy == 2 ? sat_add(S_[e.slot], e.score) : e.score;
                 uflag[e.slot] = 1;
                 w.sstat[e.w >> 32] = 1;  // UPDATED
             }
@@ -888,6 +949,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
                         if (dir) gave[cd[j]] = 1;
                     }
                 }
+                cst[j] = st[z];
             }
         }
         __syncthreads();
@@ -927,6 +989,31 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             nflag[dslot[j]] = 1;
             newk[dslot[j]] = ck[j];
             news[dslot[j]] = cs[j];
+        }
+        // entries merged into another one: the key's status (UPDATED, a candidate's, or REJECTED when
+        // 128 better inserts crowded it out) and, for find_or_insert, the key's row
+        if (any_merged) {
+            for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+                if (c0 + lane >= m) continue;
+                const Entry e = fetch_entry(w, b, c0 + lane);
+                const uint64_t x = set_slot(w, e.key);
+                const uint32_t last = atomicOr(&w.dd[x].last, 0u);
+                if (last == (uint32_t)e.w + 1u) continue;  // the key's winning entry
+                uint8_t s = 4;
+                if (e.kind == kOpUpdate) {
+                    s = 1;
+                } else {
+                    for (int j = 0; j < nbest; ++j)
+                        if (ck[j] == e.key) s = cst[j];
+                }
+                w.sstat[e.w >> 32] = s;
+                if (w.out) {
+                    const uint4* src = e.kind == kOpUpdate ? reinterpret_cast<const uint4*>(t.row(eb + e.slot))
+                                                           : reinterpret_cast<const uint4*>(vals + (size_t)(last - 1u) * t.dim);
+                    uint4* o = reinterpret_cast<uint4*>(w.out + (size_t)(uint32_t)e.w * t.dim);
+                    for (uint32_t c = 0; c < chunks; ++c) o[c] = src[c];
+                }
+            }
         }
         // rows: chunk c by lane c mod 64; the victims' rows copied out first, then the listed inserts
         if (ev.vals) {
@@ -987,24 +1074,30 @@ __global__ void __launch_bounds__(256) k_finish(UpsertWs w, uint64_t n, uint8_t*
     if (i >= n) return;
     const uint32_t p = w.slot_of[i];
     if (status) status[i] = (p == kNoSlot) ? 5 : w.sstat[p];
-    if (w.out && p != kNoSlot && w.ctr[kCtrDup]) {  // find_or_insert: a repeated key returns its last occurrence's row
+    if (!w.out || p == kNoSlot) return;
+    // find_or_insert: an occurrence returns its representative's row (local dedupe), or its key's
+    // last occurrence's (global dedupe, when a key repeated)
+    uint32_t src_pos = (uint32_t)i;
+    if (w.local) {
+        src_pos = p;
+    } else if (w.ctr[kCtrDup]) {
         const DedupeEntry de = w.dd[p];
-        const uint32_t last = (de.claim > de.last ? de.claim : de.last) - 1;
-        if (last != (uint32_t)i) {
-            const uint4* src = reinterpret_cast<const uint4*>(w.out + (size_t)last * dim);
-            uint4* dst = reinterpret_cast<uint4*>(w.out + i * dim);
-            for (uint32_t c = 0; c < (dim >> 2); ++c) dst[c] = src[c];
-        }
+        src_pos = (de.claim > de.last ? de.claim : de.last) - 1;
+    }
+    if (src_pos != (uint32_t)i) {
+        const uint4* src = reinterpret_cast<const uint4*>(w.out + (size_t)src_pos * dim);
+        uint4* dst = reinterpret_cast<uint4*>(w.out + i * dim);
+        for (uint32_t c = 0; c < (dim >> 2); ++c) dst[c] = src[c];
     }
 }
 
 template <int G>
 static void launch_route(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys, const float* vals,
-                         const uint64_t* scores, hipStream_t s, uint64_t* ev_count = nullptr) {
-    if (w.fused)
-        k_route<G, true><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores, ev_count);
+                         const uint64_t* scores, hipStream_t s) {
+    if (w.local)
+        k_route<G, true><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores);
     else
-        k_route<G, false><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores, nullptr);
+        k_route<G, false><<<blocks_for(n * G, 256), 256, 0, s>>>(t, w, n, keys, vals, scores);
 }
 
 hipError_t launch_upsert_prep(const TableView& t, const UpsertWs& w, uint64_t n, const uint64_t* keys,
@@ -1069,26 +1162,25 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
                          const uint64_t* scores, uint8_t* status, const EvictOut& ev, size_t zero_bytes, int group,
                          hipStream_t s) {
     hipError_t e;
+    if (n == 0) return hipSuccess;
     if (w.rounds > 1) {
         if ((e = launch_upsert_prep(t, w, n, keys, scores, ev, zero_bytes, s)) != hipSuccess) return e;
         if ((e = launch_upsert_rounds(t, w, n, keys, vals, scores, ev, group, s)) != hipSuccess) return e;
-    } else {  // one pass claims the dedupe entries and routes
-        if (n == 0) return hipSuccess;
-        if ((e = launch_fill_zero(w.dd, zero_bytes, s)) != hipSuccess) return e;
-        UpsertWs wf = w;
-        wf.fused = 1;
-        wf.in_scores = scores;
-        switch (group) {
-            case 4: launch_route<4>(t, wf, n, keys, vals, scores, s, ev.count); break;
-            case 16: launch_route<16>(t, wf, n, keys, vals, scores, s, ev.count); break;
-            default: launch_route<8>(t, wf, n, keys, vals, scores, s, ev.count); break;
-        }
-        const uint64_t fb = (t.nbuckets + 255) / 256;
-        k_fixup<<<(unsigned)(fb < 256 ? fb : 256), 256, 0, s>>>(t, wf, vals);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_upsert_apply(t, wf, n, vals, ev, s)) != hipSuccess) return e;
+        return launch_upsert_finish(w, n, status, t.dim, s);
     }
-    return launch_upsert_finish(w, n, status, t.dim, s);
+    // one route round: block-local dedupe, routing of the representatives, apply
+    UpsertWs wl = w;
+    wl.local = 1;
+    if ((e = launch_fill_zero(w.dd, zero_bytes, s)) != hipSuccess) return e;
+    const unsigned nblk = (unsigned)((n + kLocalKeys - 1) / kLocalKeys);
+    if (t.policy == 2)
+        k_local_dedupe<true><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count);
+    else
+        k_local_dedupe<false><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_upsert_route(t, wl, n, keys, vals, scores, group, s)) != hipSuccess) return e;
+    if ((e = launch_upsert_apply(t, wl, n, vals, ev, s)) != hipSuccess) return e;
+    return launch_upsert_finish(wl, n, status, t.dim, s);
 }
 
 }  // namespace cskv
