@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         nfree = gmax_i<GA>(has && e.kind != kOpUpdate ? (int)e.nfree : -1);
         const bool plain = nu == 0 && (int)ni <= nfree;  // only inserts, all of them direct
         uint32_t taken = 0;  // free slots before the call (now holding direct inserts) are never victims
-        if (!plain) {
+        if (!plain && nfree != 0) {
             const uint2 dv = *reinterpret_cast<const uint2*>(t.dig + eb + lane * SPL);
             taken = match4(dv.x, 0u) | (match4(dv.y, 0u) << 4);
             nfree = gsum_i<GA>(__popc(taken));
