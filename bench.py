@@ -542,7 +542,9 @@ def bench_serving(dev, log2_cap=28, dim=128, nreq=100_000, budget=4 << 30, loads
     requests of lognormal(4096, 1.0) keys clipped to 256..65536, 90 % find / 10 %
     insert_and_evict, Zipf(1.1) keys over 2^34, arriving as a Poisson process at 50 % and 80 % of
     the plain FIFO server's measured saturation rate; p50/p99 latency of the continuous-batching
-    server and of the plain server (one request per launch, one launch in flight)."""
+    server on one stream, of the same server with reader groups rotating over two streams of their
+    own (concurrent on the device), and of the plain server (one request per launch, one launch in
+    flight)."""
     cap = 1 << log2_cap
     t = cskv.Table(cap, dim, mode="dual", policy="lru", device=dev)
     b = 1 << 20
@@ -564,17 +566,21 @@ def bench_serving(dev, log2_cap=28, dim=128, nreq=100_000, budget=4 << 30, loads
     st_plain, _ = serve.serve(t, tr, budget, max_inflight_groups=1, max_merge=1, realtime=False)
     sat = nreq / st_plain["wall_s"]
     st_cb, _ = serve.serve(t, tr, budget, max_inflight_groups=2, max_merge=64, realtime=False)
+    st_rs, _ = serve.serve(t, tr, budget, max_inflight_groups=4, max_merge=64, realtime=False, reader_streams=2)
     out = {"workload": f"2^{log2_cap} slots dim {dim} LRU ({size / cap:.3f} full), {nreq} requests lognormal(4096, 1.0) "
                        f"keys in [256, 65536], 90/10 find/insert_and_evict, Zipf(1.1) over 2^34, budget {budget >> 30} GiB",
            "plain_saturation_qps": round(sat, 1), "batched_saturation_qps": round(nreq / st_cb["wall_s"], 1),
+           "batched_reader_streams_saturation_qps": round(nreq / st_rs["wall_s"], 1),
            "levels": {}}
+    servers = (("continuous_batching", 2, 64, 0), ("continuous_batching_reader_streams", 4, 64, 2), ("plain_fifo", 1, 1, 0))
     for frac in loads:
         qps = frac * sat
         arr = poisson_arrivals(40 + int(frac * 100), nreq, qps)
         row = {"qps": round(qps, 1)}
-        for name, mi, mm in (("continuous_batching", 2, 64), ("plain_fifo", 1, 1)):
+        for name, mi, mm, rsn in servers:
             trq = serve.Trace(t, ops, sizes, keys, vals, arr, shared_values=True)
-            st, times = serve.serve(t, trq, budget, max_inflight_groups=mi, max_merge=mm, realtime=True)
+            st, times = serve.serve(t, trq, budget, max_inflight_groups=mi, max_merge=mm, realtime=True,
+                                    reader_streams=rsn)
             lat = times["latency_s"][nreq // 10:]  # after warm-up
             row[name] = {**{k: round(v, 4) for k, v in serve.percentiles_ms(lat).items()},
                          "launches": int(st["groups"]), "deferred": int(st["deferred_for_memory"])}

@@ -412,11 +412,16 @@ const char* cskv_strerror(int code);
  *    bytes) fits into cfg->arena_budget_bytes together with every admitted, unfinished request;
  *    a request that does not fit waits (it is deferred, never failed); a request larger than
  *    the whole budget is refused with CSKV_EINVAL before anything runs.
- *  - Execution: admitted requests are launched in admission order on `stream` whenever fewer
- *    than cfg->max_inflight_groups groups are on the GPU.  Consecutive admitted finds merge into
- *    one reader launch of at most cfg->max_merge (<= 64) requests; each insert_and_evict is a
- *    serialization point (inserter group, Sec. 3.5).  New groups are enqueued while earlier ones
- *    run, so their work overlaps on the device.  The result of every request is exactly that of
+ *  - Execution: admitted requests are launched in admission order whenever fewer than
+ *    cfg->max_inflight_groups groups are on the GPU.  Consecutive admitted finds merge into one
+ *    reader launch of at most cfg->max_merge (<= 64) requests; each insert_and_evict is a
+ *    serialization point (inserter group, Sec. 3.5).  With cfg->reader_streams = 0 every group
+ *    runs on `stream`, in order, and new groups are enqueued while earlier ones run.  With 1..4
+ *    reader streams (created for the call at default priority, destroyed before it returns),
+ *    inserters run on `stream` and reader groups rotate over the reader streams: a reader group
+ *    waits only for the last inserter before it and an inserter for every reader group before
+ *    it (events), so reader groups between two inserters execute concurrently (Sec. 3.5: readers
+ *    are compatible with readers).  Either way the result of every request is exactly that of
  *    issuing the requests alone, one by one, in admission order.
  *  - Outputs go to the request's d_* result pointers; when those are NULL they go to a ring
  *    arena in the workspace (of arena_budget_bytes) and are recycled after completion.
@@ -451,6 +456,9 @@ typedef struct cskv_serve_config {
     uint32_t max_inflight_groups;
     uint32_t max_merge;
     int realtime;
+    uint32_t reader_streams;  /* 0: every group on `stream`; 1..4: reader groups rotate over that many
+                                 streams of their own, so that consecutive reader groups run
+                                 concurrently on the device */
 } cskv_serve_config;
 
 typedef struct cskv_serve_stats {

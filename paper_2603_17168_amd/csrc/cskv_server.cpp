@@ -1,6 +1,9 @@
 // Serving loop: real-time admission of find / insert_and_evict requests under an HBM budget,
 // continuous batching of queued finds into merged reader launches, inserts as serialization
-// points, completion by polled HIP events.  Single host thread, one stream.
+// points, completion by polled HIP events.  Single host thread; inserters on the caller's stream,
+// reader groups on it too or rotating over reader streams of their own (ordered by events: a
+// reader group after the last inserter before it, an inserter after every reader group before
+// it), so that reader groups between inserters run concurrently.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -60,7 +63,8 @@ size_t cskv_serve_workspace_bytes(const cskv_table* table, uint64_t max_request_
 int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const cskv_serve_config* cfg, void* d_ws,
                      size_t ws_bytes, void* stream, cskv_serve_stats* stats) {
     if (!t || (!reqs && nreq) || !cfg || !d_ws || ((uintptr_t)d_ws & 255)) return CSKV_EINVAL;
-    if (cfg->max_merge == 0 || cfg->max_merge > (uint32_t)kMaxArgDescs || cfg->max_inflight_groups == 0)
+    if (cfg->max_merge == 0 || cfg->max_merge > (uint32_t)kMaxArgDescs || cfg->max_inflight_groups == 0 ||
+        cfg->reader_streams > 4)
         return CSKV_EINVAL;
     const uint32_t dim = t->view.dim;
     uint64_t max_n = 1;
@@ -102,6 +106,25 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
         }
         return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     };
+
+    // reader streams (default priority) and the events that order them against the inserters:
+    // `writer` is recorded after every inserter (and at the start), `tail[k]` after every reader
+    // group on stream k; `waited[k]` is the inserter count stream k last waited for
+    const uint32_t K = cfg->reader_streams;
+    hipStream_t rs[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t tail[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t writer = nullptr;
+    uint64_t writers = 0, waited[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    bool dirty[4] = {false, false, false, false};
+    uint32_t next_rs = 0;
+    if (K) {
+        bool ok = hipEventCreateWithFlags(&writer, hipEventDisableTiming) == hipSuccess &&
+                  hipEventRecord(writer, s) == hipSuccess;
+        for (uint32_t k = 0; k < K && ok; ++k)
+            ok = hipStreamCreateWithFlags(&rs[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&tail[k], hipEventDisableTiming) == hipSuccess;
+        if (!ok) rc = CSKV_EHIP;
+    }
 
     while (next_complete < nreq && rc == CSKV_OK) {
         bool progress = false;
@@ -153,7 +176,20 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
             Group g;
             g.first = next_launch;
             const double tl = now_s(t0);
+            hipStream_t q = s;  // the group's stream
+            uint32_t qk = 0;    // and, for a reader group on a reader stream, that stream's index
             if (reqs[next_launch].op == CSKV_REQ_FIND) {
+                if (K) {  // the next reader stream, after the last inserter before this group
+                    const uint32_t k = next_rs;
+                    qk = k;
+                    next_rs = (next_rs + 1) % K;
+                    q = rs[k];
+                    if (waited[k] != writers) {
+                        if (hipStreamWaitEvent(q, writer, 0) != hipSuccess) rc = CSKV_EHIP;
+                        waited[k] = writers;
+                    }
+                    dirty[k] = true;
+                }
                 FindDescArgs a{};
                 a.nd = 0;
                 a.total = 0;
@@ -165,20 +201,31 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
                     r.group = (uint32_t)st.groups;
                     ++next_launch;
                 }
-                if (launch_find_args(t->view, a, t->group, t->prefetch_b2, s) != hipSuccess) rc = CSKV_EHIP;
+                if (rc == CSKV_OK && launch_find_args(t->view, a, t->group, t->prefetch_b2, q) != hipSuccess)
+                    rc = CSKV_EHIP;
+                if (K && rc == CSKV_OK && hipEventRecord(tail[qk], q) != hipSuccess) rc = CSKV_EHIP;
                 ++st.reader_launches;
             } else {
+                for (uint32_t k = 0; k < K && rc == CSKV_OK; ++k)  // after every reader group before it
+                    if (dirty[k]) {
+                        if (hipStreamWaitEvent(s, tail[k], 0) != hipSuccess) rc = CSKV_EHIP;
+                        dirty[k] = false;
+                    }
                 cskv_request& r = reqs[next_launch];
                 UpsertArgs ua{r.n, r.d_keys, r.d_values, r.d_scores, r.d_flags,
                               EvictOut{r.d_ev_keys, r.d_ev_values, r.d_ev_scores, r.d_n_evicted}};
-                rc = enqueue_upsert(t, ua, ws, ups_bytes, s);
+                if (rc == CSKV_OK) rc = enqueue_upsert(t, ua, ws, ups_bytes, s);
+                if (K && rc == CSKV_OK) {
+                    if (hipEventRecord(writer, s) != hipSuccess) rc = CSKV_EHIP;
+                    ++writers;
+                }
                 r.launch_s = tl;
                 r.group = (uint32_t)st.groups;
                 ++next_launch;
                 ++st.inserter_launches;
             }
             g.last = next_launch;
-            if (rc == CSKV_OK && (!get_event(&g.done) || hipEventRecord(g.done, s) != hipSuccess)) rc = CSKV_EHIP;
+            if (rc == CSKV_OK && (!get_event(&g.done) || hipEventRecord(g.done, q) != hipSuccess)) rc = CSKV_EHIP;
             if (rc != CSKV_OK) break;
             inflight.push_back(g);
             ++st.groups;
@@ -207,7 +254,20 @@ int cskv_serve_trace(cskv_table* t, cskv_request* reqs, uint64_t nreq, const csk
         }
         (void)progress;
     }
-    if (rc != CSKV_OK) (void)hipStreamSynchronize(s);
+    // the caller's stream (and the role lock's release on it) follows every reader group
+    for (uint32_t k = 0; k < K; ++k) {
+        if (rs[k] && tail[k] && hipEventRecord(tail[k], rs[k]) == hipSuccess) (void)hipStreamWaitEvent(s, tail[k], 0);
+    }
+    if (rc != CSKV_OK || K) {
+        for (uint32_t k = 0; k < K; ++k)
+            if (rs[k]) (void)hipStreamSynchronize(rs[k]);
+        (void)hipStreamSynchronize(s);
+    }
+    for (uint32_t k = 0; k < K; ++k) {
+        if (tail[k]) (void)hipEventDestroy(tail[k]);
+        if (rs[k]) (void)hipStreamDestroy(rs[k]);
+    }
+    if (writer) (void)hipEventDestroy(writer);
     for (auto& g : inflight) event_pool.push_back(g.done);
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     st.wall_s = now_s(t0);

@@ -25,7 +25,7 @@ class Request(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("arena_budget_bytes", ctypes.c_uint64), ("max_inflight_groups", ctypes.c_uint32),
-                ("max_merge", ctypes.c_uint32), ("realtime", ctypes.c_int)]
+                ("max_merge", ctypes.c_uint32), ("realtime", ctypes.c_int), ("reader_streams", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -114,7 +114,7 @@ class Trace:
 
 
 def serve(table: cskv.Table, trace: Trace, budget_bytes=4 << 30, max_inflight_groups=2, max_merge=64,
-          realtime=True, stream=None):
+          realtime=True, stream=None, reader_streams=0):
     """Run the trace; returns (stats dict, per-request arrays: latency_s, admit_s, launch_s, complete_s, seq, group)."""
     L = _lib()
     reqs = trace.requests()
@@ -122,7 +122,7 @@ def serve(table: cskv.Table, trace: Trace, budget_bytes=4 << 30, max_inflight_gr
     max_n = int(trace.sizes.max()) if n else 1
     need = int(L.cskv_serve_workspace_bytes(table._h, max_n, budget_bytes))
     ws = torch.empty(need, dtype=torch.uint8, device=table.device)
-    cfg = Config(budget_bytes, max_inflight_groups, max_merge, 1 if realtime else 0)
+    cfg = Config(budget_bytes, max_inflight_groups, max_merge, 1 if realtime else 0, reader_streams)
     st = Stats()
     s = stream if stream is not None else torch.cuda.current_stream(table.device)
     torch.cuda.synchronize(table.device)

@@ -219,16 +219,30 @@ class OracleRun:
         self.name = name
         self.q: queue.Queue = queue.Queue()
         self.t0 = time.time()
+        self.halt = threading.Event()
         self.th = threading.Thread(target=self._run, args=(scenario, side_factory), daemon=True, name=name)
         self.th.start()
 
     def _run(self, scenario, side_factory):
         try:
             for lab, rec in scenario(side_factory()):
+                if self.halt.is_set():
+                    return
                 self.q.put((lab, rec))
             self.q.put(("__end__", None))
         except BaseException as e:  # surfaced in the test thread
             self.q.put(("__error__", e))
+
+    def stop(self, timeout: float = 300.0):
+        """Ends the scenario after its current oracle call (a run whose records no test consumed
+        must not outlive the test session: native code still running at interpreter exit aborts it)."""
+        self.halt.set()
+        while True:  # drain, so that a producer blocked on nothing keeps going to its next check
+            try:
+                self.q.get_nowait()
+            except queue.Empty:
+                break
+        self.th.join(timeout)
 
     def records(self):
         while True:

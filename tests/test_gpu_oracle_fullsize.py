@@ -15,7 +15,8 @@ instantiates them), compared with the sequential oracle call by call and table b
   CSKV_C3_STEPS) so that the whole file fits one test run.
 * C5 - the serving loop's serialization order replayed through the oracle: 10^4 requests
   (lognormal(4096, 1.0) sizes clipped to 256-65536, 90 % find / 10 % insert_and_evict, Zipf(1.1)
-  keys over 2^34, Poisson arrivals) on a 2^22-slot dim-32 LRU table filled with ranks 1..2^22.
+  keys over 2^34, Poisson arrivals, reader groups on two streams of their own) on a 2^22-slot
+  dim-32 LRU table filled with ranks 1..2^22.
 
 Rows are compared through value-ids: every inserted occurrence carries its own id, and the GPU's
 rows must equal the generator's rows of the ids the oracle holds.  The oracle side of each
@@ -210,6 +211,8 @@ def oracle_runs():
     }
     runs["C5"].trace = c5
     yield runs
+    for r in runs.values():
+        r.stop()
 
 
 def release(*objs):
@@ -303,8 +306,8 @@ def test_c5_serving_order_replayed_through_oracle(oracle_runs):
         tr = serve.Trace(side.t, ops, sizes, kd, vals, arrivals, with_results=True)
         tr.find_out.view(torch.int32).fill_(fs.NAN_BITS)
         say(f"C5: serving {C5_NREQ} requests ({int(sizes.sum())} keys)")
-        stats, times = serve.serve(side.t, tr, budget_bytes=1 << 30, max_inflight_groups=2, max_merge=64,
-                                   realtime=True)
+        stats, times = serve.serve(side.t, tr, budget_bytes=1 << 30, max_inflight_groups=4, max_merge=64,
+                                   realtime=True, reader_streams=2)
         say(f"C5: served, {stats}")
         assert stats["completed"] == C5_NREQ
         # the oracle replays arrival order: the loop must have serialized requests in that order

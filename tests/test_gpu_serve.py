@@ -1,6 +1,6 @@
 """Serving loop: every request's result is the same alone (issued by itself, in admission order)
-and in the mix (merged reader launches, overlapping groups, budget-deferred admission), and equals
-the oracle."""
+and in the mix (merged reader launches, overlapping groups, reader groups on streams of their own
+running concurrently, budget-deferred admission), and equals the oracle."""
 import sys
 
 import numpy as np
@@ -52,8 +52,9 @@ def clone(src):
     return dst
 
 
+@pytest.mark.parametrize("streams", [0, 2])
 @pytest.mark.parametrize("mode", ["realtime", "burst", "tight_budget"])
-def test_serving_alone_equals_mix_and_oracle(mode):
+def test_serving_alone_equals_mix_and_oracle(mode, streams):
     cap, dim = 1 << 15, 16
     base = cskv.Table(cap, dim, "dual", "lru")
     pre = prefill(base, 30000)
@@ -66,9 +67,9 @@ def test_serving_alone_equals_mix_and_oracle(mode):
     ops, sizes, keys, vals, arr = make_trace(base, nreq, seed=11, qps=20000.0)
     tr = serve.Trace(base, ops, sizes, keys, vals, arr, with_results=True)
     budget = 1 << 20 if mode == "tight_budget" else 256 << 20
-    say(f"serving {nreq} requests, mode {mode}")
-    stats, times = serve.serve(base, tr, budget_bytes=budget, max_inflight_groups=2, max_merge=16,
-                               realtime=(mode == "realtime"))
+    say(f"serving {nreq} requests, mode {mode}, reader streams {streams}")
+    stats, times = serve.serve(base, tr, budget_bytes=budget, max_inflight_groups=4 if streams else 2, max_merge=16,
+                               realtime=(mode == "realtime"), reader_streams=streams)
     say(stats)
     assert stats["completed"] == nreq
     assert np.array_equal(times["seq"], np.arange(nreq))  # admission order = arrival order
