@@ -165,6 +165,28 @@ int cskv_insert_or_assign(cskv_table* table, uint64_t n, const uint64_t* d_keys,
                           void* stream);
 
 /*
+ * insert_or_assign that allocates nothing, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same inputs,
+ * outputs, semantics and kernels as cskv_insert_or_assign; the workspace is instead a fixed
+ * device array of the library, CSKV_NOALLOC_SCRATCH_BYTES (12 MiB) per GPU, allocated when the
+ * library's code loads on that GPU and held until the process ends.  The call makes no
+ * hipMalloc / hipFree and calls no allocating routine.  n is at most CSKV_NOALLOC_MAX_KEYS
+ * (65536): a larger n returns CSKV_EINVAL and launches nothing (CSKV_ENOMEM if the workspace
+ * would not fit, which this limit rules out).  The array keeps the last call's contents; every
+ * call clears what must start at zero, with a fill kernel on its stream.  All calls on one GPU
+ * share the array, whatever the table or stream: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and give undefined results; order them on one stream or
+ * with events.  The first call on a GPU looks up the array's address there (hipGetSymbolAddress,
+ * with that GPU current) and keeps it; a failure returns CSKV_EHIP.
+ */
+#define CSKV_NOALLOC_MAX_KEYS 65536u
+#define CSKV_NOALLOC_SCRATCH_BYTES (12u << 20)
+int cskv_insert_or_assign_noalloc(cskv_table* table, uint64_t n, const uint64_t* d_keys, const float* d_values,
+                                  const uint64_t* d_scores, uint8_t* d_status, void* stream);
+/* bytes of the fixed array above (CSKV_NOALLOC_SCRATCH_BYTES) */
+size_t cskv_noalloc_scratch_bytes(void);
+
+/*
  * insert_and_evict (Sec. 4.1: insert_or_assign that also returns what it evicted).
  * Same inputs as insert_or_assign; d_status is required.  Every entry displaced by the call
  * is written to d_ev_keys[j], d_ev_scores[j] (the score it had, after any update in the same

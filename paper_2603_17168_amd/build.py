@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcskv.so")
-SOURCES = ["cskv_find.hip", "cskv_access.hip", "cskv_kernels.hip", "cskv_upsert.hip", "cskv_probe.hip", "cskv_api.cpp",
+SOURCES = ["cskv_find.hip", "cskv_access.hip", "cskv_kernels.hip", "cskv_upsert.hip", "cskv_noalloc.hip", "cskv_probe.hip", "cskv_api.cpp",
            "cskv_program.cpp", "cskv_server.cpp", "cskv_mt.cpp"]
 
 HIPCC_FLAGS = [

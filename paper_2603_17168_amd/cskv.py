@@ -25,6 +25,7 @@ OP_FIND, OP_INSERT_OR_ASSIGN, OP_INSERT_AND_EVICT, OP_ERASE, OP_ASSIGN, OP_FIND_
 TUNE = {"find_group": 1, "route_group": 2, "find_prefetch_b2": 3, "find_blocks_per_cu": 4, "find_pairs": 5, "find_digest": 6}
 ST_UPDATED, ST_INSERTED, ST_INSERTED_EVICT, ST_REJECTED, ST_INVALID_KEY = 1, 2, 3, 4, 5
 LOCK = {"none": 0, "triple_group": 1, "reader_writer": 2}
+NOALLOC_MAX_KEYS = 65536  # CSKV_NOALLOC_MAX_KEYS
 MT_OP = {"find": 0, "assign": 1, "insert_erase": 2}
 
 _lib = None
@@ -52,6 +53,8 @@ def lib():
         "cskv_workspace_bytes": (SZ, [P, I, U64]),
         "cskv_find": (I, [P, U64, P, P, P, P, P]),
         "cskv_insert_or_assign": (I, [P, U64, P, P, P, P, P, SZ, P]),
+        "cskv_insert_or_assign_noalloc": (I, [P, U64, P, P, P, P, P]),
+        "cskv_noalloc_scratch_bytes": (SZ, []),
         "cskv_insert_and_evict": (I, [P, U64, P, P, P, P, P, P, P, P, P, SZ, P]),
         "cskv_erase": (I, [P, U64, P, P, P, SZ, P]),
         "cskv_size": (I, [P, P, P]),
@@ -281,6 +284,22 @@ class Table:
         with torch.cuda.device(self.device):
             _check(lib().cskv_insert_or_assign(self._h, n, _ptr(keys), _ptr(values), _ptr(scores), _ptr(status_out),
                                                _ptr(ws), ws.numel(), _stream(self.device)), "cskv_insert_or_assign")
+        return status_out
+
+    def insert_or_assign_noalloc(self, keys, values, scores=None, status_out=None, want_status=True):
+        """cskv_insert_or_assign_noalloc: insert_or_assign with the library's fixed workspace
+        (at most NOALLOC_MAX_KEYS keys; no workspace tensor is allocated)."""
+        keys = _as_i64(keys, self.device)
+        n = keys.numel()
+        values = self._vals(values, n)
+        if scores is not None:
+            scores = _as_i64(scores, self.device)
+        if status_out is None and want_status:
+            status_out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().cskv_insert_or_assign_noalloc(self._h, n, _ptr(keys), _ptr(values), _ptr(scores),
+                                                       _ptr(status_out), _stream(self.device)),
+                   "cskv_insert_or_assign_noalloc")
         return status_out
 
     def insert_and_evict(self, keys, values, scores=None, out=None):

@@ -34,7 +34,7 @@ static uint32_t inline_capacity(uint64_t n, uint64_t nb) {
     return c;
 }
 
-UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds) {
+UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds, bool compact) {
     UpsertLayout L;
     uint64_t P = 64;
     int logP = 6;
@@ -44,7 +44,7 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds) {
     }
     L.P = P;
     L.logP = logP;
-    L.cap = inline_capacity(n, nb);
+    L.cap = compact ? 0u : inline_capacity(n, nb);
     const uint64_t nl = nb * L.cap;
     const uint64_t nslow = n < nb ? n : nb;
     size_t o = 0;
@@ -66,7 +66,7 @@ UpsertLayout upsert_layout(uint64_t n, uint64_t nb, uint32_t rounds) {
     L.off_touched = o; o = align256(o + nslow * 4);
     L.off_rank = o;    o = align256(o + (rounds > 1 ? n * 4 : 0));
     L.off_bsum = o;    o = align256(o + (rounds > 1 ? ((n + 255) / 256) * 4 : 0));
-    L.list_mode = n * 4 <= nb;  // apply visits only the touched buckets (route lists them)
+    L.list_mode = compact || n * 4 <= nb;  // apply visits only the touched buckets (route lists them)
     L.total = o;
     return L;
 }
@@ -241,7 +241,7 @@ int cskv_find(cskv_table* table, uint64_t n, const uint64_t* d_keys, float* d_va
 namespace cskv {
 
 int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, UpsertWs* out,
-                size_t* zero_out, bool need_vals) {
+                size_t* zero_out, bool need_vals, bool compact) {
     const uint64_t n = a.n;
     if (!table || !n_ok(n)) return CSKV_EINVAL;
     if (n == 0) return CSKV_OK;
@@ -250,7 +250,7 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     if (!aligned(a.keys, 8) || (a.vals && !aligned(a.vals, 16)) || !aligned(d_ws, 256) ||
         (a.scores && !aligned(a.scores, 8)) || (a.out && !aligned(a.out, 16)))
         return CSKV_EINVAL;
-    const UpsertLayout L = upsert_layout(n, table->view.nbuckets, table->subrounds);
+    const UpsertLayout L = upsert_layout(n, table->view.nbuckets, table->subrounds, compact);
     if (ws_bytes < L.total) return CSKV_ENOMEM;
     uint8_t* b = reinterpret_cast<uint8_t*>(d_ws);
     UpsertWs& w = *out;
@@ -280,10 +280,11 @@ int plan_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_by
     return CSKV_OK;
 }
 
-int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream, int group) {
+int enqueue_upsert(cskv_table* table, const UpsertArgs& a, void* d_ws, size_t ws_bytes, hipStream_t stream, int group,
+                   bool compact) {
     UpsertWs w;
     size_t zero_bytes = 0;
-    const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes);
+    const int rc = plan_upsert(table, a, d_ws, ws_bytes, &w, &zero_bytes, true, compact);
     if (rc != CSKV_OK || a.n == 0) return rc;
     return hip_rc(launch_upsert(table->view, w, a.n, a.keys, a.vals, a.scores, a.status, a.ev, zero_bytes,
                                 group > 0 ? group : table->route_group, stream));

@@ -150,7 +150,9 @@ struct UpsertLayout {
 };
 
 StorageLayout storage_layout(uint64_t nbuckets, uint32_t dim, uint64_t hbm_rows);
-UpsertLayout upsert_layout(uint64_t n, uint64_t nbuckets, uint32_t rounds = 1);
+// compact: no per-bucket inline lists (every list position in the hashed overflow table) and the
+// apply visits only the touched buckets, so that the size depends on n alone
+UpsertLayout upsert_layout(uint64_t n, uint64_t nbuckets, uint32_t rounds = 1, bool compact = false);
 size_t erase_ws_bytes(uint64_t n);
 
 // launchers (return hipError_t of the last launch)
@@ -273,9 +275,11 @@ class RoleScope {
 namespace cskv {
 // validates an upsert and lays out its workspace (CSKV_* code)
 int plan_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, UpsertWs* w, size_t* zero_bytes,
-                bool need_vals = true);
+                bool need_vals = true, bool compact = false);
 // group: lanes per key of the routing (upsert) or probe (erase) kernel; -1 = the table's setting
-int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s, int group = -1);
+// compact: the workspace layout sized by n alone (upsert_layout)
+int enqueue_upsert(cskv_table* t, const UpsertArgs& a, void* ws, size_t ws_bytes, hipStream_t s, int group = -1,
+                   bool compact = false);
 int enqueue_erase(cskv_table* t, uint64_t n, const uint64_t* keys, uint8_t* erased, void* ws, size_t ws_bytes,
                   hipStream_t s, int group = -1);
 }  // namespace cskv
