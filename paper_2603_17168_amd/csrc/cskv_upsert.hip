@@ -18,10 +18,15 @@
 //            sees the digest lines, occupancies and free-slot order of the table before it.
 //            Routing depends only on the key and that table, so the representatives of a key
 //            repeated across blocks all land in the same bucket's list.
-//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block.  The entries of
-//            one key are merged first: the one with the largest input position (the key's last
-//            occurrence) wins, LFU increments are summed.  A bucket that received only inserts,
-//            no more than its free slots, just has the digest bytes of its direct inserts written.
+//            Routing also writes each representative's status as far as it knows it (UPDATED,
+//            INSERTED for a direct insert).
+//   commit   one thread per bucket: a bucket that received only direct inserts of distinct keys
+//            and keeps a free slot is finished by writing their digest bytes
+//   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block, for the buckets
+//            the commit left.  The entries of one key are merged first: the one with the largest
+//            input position (the key's last occurrence) wins, LFU increments are summed.  A bucket
+//            that received only inserts, no more than its free slots, just has the digest bytes of
+//            its direct inserts written.
 //            Otherwise: updates, then inserts ranked by (score desc, key asc): the first ones (as
 //            many as there were free slots) are inserted, the rest compete with the smallest
 //            residents by (score, key) - strict admission.  Slot positions are not observable,
@@ -399,6 +404,9 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
     if (lane == 0) {
         const uint64_t wv = ((uint64_t)p << 32) | (uint32_t)i;
         const uint32_t kind = upd ? kOpUpdate : (direct ? kOpDirect : kOpListed);
+        // local dedupe: the status as far as routing knows it, in input order (an update's is final;
+        // the apply kernels rewrite the others' unless the commit pass finishes the bucket)
+        if constexpr (LOCAL) w.sstat[i] = upd ? 1 : (direct ? 2 : 0);
         const uint32_t es = eslot >= 0 ? (uint32_t)eslot : 0u;
         if (r < w.cap) {
             store_entry(w.il + (size_t)tgt * w.cap + r, k, ns, wv, es, h.dg, kind, (uint32_t)nfree);
@@ -425,8 +433,68 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
 }
 
 // ------------------------------------------------------------------------------------------
+// commit pass: one thread per bucket (or per touched-list position).  A bucket whose operations
+// are all direct inserts of distinct keys that leave it with a free slot is finished here: its
+// keys, scores and rows are in place, so only the digest bytes remain (and the statuses, unless
+// routing wrote them); its counter is cleared, so the fast apply that follows skips it.  Any
+// other bucket (an update, a listed insert, a key with entries from two input blocks, a bucket
+// that fills up, more than 16 operations, find_or_insert) is left to the apply kernels, which
+// rewrite all its statuses.  A bucket whose cached minimum is set was full when last written and
+// most likely still is, so its entries are not read.
+constexpr int kLiteMax = 8;  // operations of a bucket that one thread commits
+
+__global__ void __launch_bounds__(256) k_apply_commit(TableView t, UpsertWs w) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t total = w.list_mode ? (uint64_t)w.ctr[kCtrTouched] : t.nbuckets;
+    if (j >= total || w.out) return;
+    const uint32_t b = w.list_mode ? w.touched[j] : (uint32_t)j;
+    const uint64_t c = t.cnt[b];
+    const uint32_t ni = (uint32_t)c, nu = (uint32_t)(c >> 32);
+    if (ni == 0 || nu != 0 || ni > (uint32_t)kLiteMax || t.bmin[2 * (size_t)b + 1] != 0) return;
+    bool ok = true;
+    uint64_t k[kLiteMax];
+    uint32_t sd[kLiteMax];  // slot | digest << 8
+#pragma unroll
+    for (int r = 0; r < kLiteMax; ++r) {
+        k[r] = 0;
+        sd[r] = 0;
+        if (ok && r < (int)ni) {
+            const Entry e = fetch_entry(w, b, (uint32_t)r);
+            ok = e.kind == kOpDirect && (uint32_t)e.nfree > ni;
+            k[r] = e.key;
+            sd[r] = (uint32_t)e.slot | ((uint32_t)e.dg << 8);
+            if (!w.local) w.sstat[e.w >> 32] = 2;  // INSERTED (the apply kernels rewrite it if need be)
+        }
+    }
+#pragma unroll
+    for (int r = 1; r < kLiteMax; ++r)
+#pragma unroll
+        for (int q = 0; q < r; ++q) ok = ok && !(r < (int)ni && k[q] == k[r]);
+    if (!ok) return;
+    const size_t eb = (size_t)b * kSlots;
+#pragma unroll
+    for (int r = 0; r < kLiteMax; ++r)
+        if (r < (int)ni) t.dig[eb + (sd[r] & 0xFFu)] = (uint8_t)(sd[r] >> 8);
+    t.cnt[b] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
 // fast apply: one 16-lane group per bucket with 1..16 operations
 constexpr int kApplyGroups = 16;  // buckets (16-lane groups) per 256-thread block
+
+// the lane's 8 slots of the bucket's score line (into registers) and key line (into LDS)
+__device__ __forceinline__ void load_lines(const TableView& t, size_t eb, int lane, uint64_t (&sc)[SPL], uint64_t* kc) {
+    const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
+    const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(t.keys + eb + lane * SPL);
+#pragma unroll
+    for (int z = 0; z < SPL / 2; ++z) {
+        const ulonglong2 v = sp[z], u = kp[z];
+        sc[2 * z] = v.x;
+        sc[2 * z + 1] = v.y;
+        kc[2 * z] = u.x;
+        kc[2 * z + 1] = u.y;
+    }
+}
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_apply_fast(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
     __shared__ uint32_t s_nev[kApplyGroups];
@@ -522,16 +590,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             }
         }
         if (full_after) {  // scores and keys of the bucket (direct inserts included), updates applied
-            const ulonglong2* sp = reinterpret_cast<const ulonglong2*>(t.scores + eb + lane * SPL);
-            const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(t.keys + eb + lane * SPL);
-#pragma unroll
-            for (int z = 0; z < SPL / 2; ++z) {
-                const ulonglong2 v = sp[z], u = kp[z];
-                sc[2 * z] = v.x;
-                sc[2 * z + 1] = v.y;
-                kc[2 * z] = u.x;
-                kc[2 * z + 1] = u.y;
-            }
+            load_lines(t, eb, lane, sc, kc);
             for (uint32_t ub = upd_bits; ub; ub &= ub - 1) {
                 const int x = __ffs(ub) - 1;
                 const int us = __shfl((int)e.slot, x, GA);
@@ -1124,6 +1183,7 @@ hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n
                                hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint64_t visit = w.list_mode ? (n < t.nbuckets ? n : t.nbuckets) : t.nbuckets;
+    k_apply_commit<<<(unsigned)((visit + 255) / 256), 256, 0, s>>>(t, w);
     k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
     uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
     if (slow_blocks > 2048) slow_blocks = 2048;
