@@ -3,10 +3,10 @@
 // Alg. 3 (score-based dual-bucket choice), under the deterministic batch order of cskv.h.
 //
 // A plain call (one route round) is a fixed sequence on one stream:
-//   zero     one fill of the call's scratch (dedupe set, overflow keys, counters)
 //   dedupe   block-local, in LDS: each block of 1024 input positions keeps one representative per
 //            key, its last occurrence in the block (and, for LFU, the block's sum of the key's
-//            increments); no global atomic per key
+//            increments); no global atomic per key.  The same launch clears the call's zeroed
+//            scratch (dedupe set, overflow keys, counters), which it does not read
 //   route    G lanes per representative, against the table as it was before the call: update slot
 //            if present in b1/b2, else target by phase D1 (occupancy, b1 on a tie) or D2 (the
 //            smaller cached bucket minimum (score, key)).  One atomic on the target's counter
@@ -142,12 +142,12 @@ constexpr int kLocalHash = 2048;
 
 template <bool LFU>
 __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
-                                                      const uint64_t* __restrict__ scores, uint64_t* ev_count) {
+                                                      const uint64_t* __restrict__ scores, uint64_t* ev_count,
+                                                      uint4* zero, size_t zero16) {
     __shared__ unsigned long long hk[kLocalHash];
     __shared__ uint32_t hl[kLocalHash];
     __shared__ unsigned long long hi[LFU ? kLocalHash : 1];
     __shared__ uint32_t hs[LFU ? kLocalHash : 1];
-    __shared__ int repeated;
     const int tid = threadIdx.x;
     for (int j = tid; j < kLocalHash; j += 256) {
         hk[j] = 0ull;
@@ -157,8 +157,10 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
             hs[j] = 0u;
         }
     }
-    if (tid == 0) repeated = 0;
     if (blockIdx.x == 0 && tid == 0 && ev_count) *ev_count = 0;
+    // the call's zeroed scratch (dedupe set, overflow keys, counters), which this pass does not use
+    for (size_t z = (size_t)blockIdx.x * 256 + tid; z < zero16; z += (size_t)gridDim.x * 256)
+        zero[z] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kLocalKeys;
     constexpr int PER = kLocalKeys / 256;
@@ -175,10 +177,7 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
         for (int probes = 0; probes < kLocalHash; ++probes) {
             const unsigned long long old = atomicCAS(&hk[h], 0ull, (unsigned long long)k);
             if (old == 0ull) break;
-            if (old == k) {
-                repeated = 1;
-                break;
-            }
+            if (old == k) break;
             h = (h + 1) & (kLocalHash - 1);
         }
         hslot[q] = (int)h;
@@ -203,7 +202,6 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
         if constexpr (LFU)
             if (rep == i) w.rinc[i] = hs[hslot[q]] ? ~0ull : hi[hslot[q]];
     }
-    if (tid == 0 && repeated) w.ctr[kCtrDup] = 1;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1231,12 +1229,12 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
     // one route round: block-local dedupe, routing of the representatives, apply
     UpsertWs wl = w;
     wl.local = 1;
-    if ((e = launch_fill_zero(w.dd, zero_bytes, s)) != hipSuccess) return e;
+    uint4* zero = reinterpret_cast<uint4*>(w.dd);  // the dedupe pass clears the scratch (a multiple of 256 bytes)
     const unsigned nblk = (unsigned)((n + kLocalKeys - 1) / kLocalKeys);
     if (t.policy == 2)
-        k_local_dedupe<true><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count);
+        k_local_dedupe<true><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
     else
-        k_local_dedupe<false><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count);
+        k_local_dedupe<false><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_upsert_route(t, wl, n, keys, vals, scores, group, s)) != hipSuccess) return e;
     if ((e = launch_upsert_apply(t, wl, n, vals, ev, s)) != hipSuccess) return e;
