@@ -799,7 +799,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
 
 // ------------------------------------------------------------------------------------------
 // slow apply: one wave per bucket with more than 16 operations
+// the merge table of one crowded bucket's keys in the slow apply (LDS); a bucket with more distinct
+// keys than it holds merges through the call's dedupe set in HBM instead
+constexpr int kSlowKeys = 512;
+
+__device__ __forceinline__ uint32_t slow_hash(uint64_t k) { return (uint32_t)((fmix64(k) * kGold) >> (64 - 9)); }
+
+// the merge-table slot of key k, claimed if new; -1 if the table is full
+__device__ __forceinline__ int slow_claim(unsigned long long* hk, uint64_t k) {
+    uint32_t h = slow_hash(k);
+    for (int probes = 0; probes < kSlowKeys; ++probes) {
+        const unsigned long long old = atomicCAS(&hk[h], 0ull, (unsigned long long)k);
+        if (old == 0ull || old == k) return (int)h;
+        h = (h + 1) & (kSlowKeys - 1);
+    }
+    return -1;
+}
+
+// the merge-table slot of key k, which is present
+__device__ __forceinline__ int slow_find(const unsigned long long* hk, uint64_t k) {
+    uint32_t h = slow_hash(k);
+    for (int probes = 0; probes < kSlowKeys && hk[h] != k; ++probes) h = (h + 1) & (kSlowKeys - 1);
+    return (int)h;
+}
+
 __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, const float* __restrict__ vals, EvictOut ev) {
+    __shared__ unsigned long long hk[kSlowKeys];  // merge table: key, largest position + 1, LFU sum
+    __shared__ uint32_t hl[kSlowKeys];
+    __shared__ unsigned long long hi[kSlowKeys];
+    __shared__ uint32_t hs[kSlowKeys];
+    __shared__ int hfull;
     __shared__ uint64_t cs[192], ck[192], cw[192];  // insert candidates: score, key, w
     __shared__ uint8_t cd[192];                     // and the free slot a direct insert took (0xFF: listed)
     __shared__ uint64_t ns_[128], nk_[128], nw_[128];
@@ -834,22 +863,50 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         const int occ = __popcll(__ballot(o0)) + __popcll(__ballot(o1));
         const int nfree = kSlots - occ;
 
-        // block-local dedupe leaves one entry per key and input block: merge a key's entries through
-        // the call's dedupe set (largest position + 1 in `last`, LFU increments summed in minc)
+        // block-local dedupe leaves one entry per key and input block: merge a key's entries (largest
+        // position + 1 wins, LFU increments summed, saturating) in the LDS merge table, or, when the
+        // bucket has more distinct keys than it holds, through the call's dedupe set
         bool any_merged = false;
+        bool in_lds = true;
         if (w.local) {
+            for (int j = lane; j < kSlowKeys; j += 64) {
+                hk[j] = 0ull;
+                hl[j] = 0u;
+                hi[j] = 0ull;
+                hs[j] = 0u;
+            }
+            if (lane == 0) hfull = 0;
+            __syncthreads();
             for (uint32_t c0 = 0; c0 < m; c0 += 64) {
                 if (c0 + lane >= m) continue;
                 const Entry e = fetch_entry(w, b, c0 + lane);
-                const uint64_t x = set_slot(w, e.key);
-                atomicMax(&w.dd[x].last, (uint32_t)e.w + 1u);
+                const int x = slow_claim(hk, e.key);
+                if (x < 0) {
+                    hfull = 1;
+                    continue;
+                }
+                atomicMax(&hl[x], (uint32_t)e.w + 1u);
                 if (t.policy == 2) {
-                    const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x),
-                                                             (unsigned long long)e.score);
-                    if (old + e.score < old) atomicOr(w.sat + x, 1u);
+                    const unsigned long long old = atomicAdd(&hi[x], (unsigned long long)e.score);
+                    if (old + e.score < old) atomicOr(&hs[x], 1u);
                 }
             }
-            __threadfence();
+            __syncthreads();
+            in_lds = hfull == 0;
+            if (!in_lds) {
+                for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+                    if (c0 + lane >= m) continue;
+                    const Entry e = fetch_entry(w, b, c0 + lane);
+                    const uint64_t x = set_slot(w, e.key);
+                    atomicMax(&w.dd[x].last, (uint32_t)e.w + 1u);
+                    if (t.policy == 2) {
+                        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x),
+                                                                 (unsigned long long)e.score);
+                        if (old + e.score < old) atomicOr(w.sat + x, 1u);
+                    }
+                }
+                __threadfence();
+            }
         }
         __syncthreads();
 
@@ -862,9 +919,15 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             if (has) e = fetch_entry(w, b, c0 + lane);
             bool live = has;
             if (has && w.local) {
-                const uint64_t x = set_slot(w, e.key);
-                live = atomicOr(&w.dd[x].last, 0u) == (uint32_t)e.w + 1u;
-                if (live && t.policy == 2) e.score = atomicOr(w.sat + x, 0u) ? ~0ull : atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x), 0ull);
+                if (in_lds) {
+                    const int x = slow_find(hk, e.key);
+                    live = hl[x] == (uint32_t)e.w + 1u;
+                    if (live && t.policy == 2) e.score = hs[x] ? ~0ull : hi[x];
+                } else {
+                    const uint64_t x = set_slot(w, e.key);
+                    live = atomicOr(&w.dd[x].last, 0u) == (uint32_t)e.w + 1u;
+                    if (live && t.policy == 2) e.score = atomicOr(w.sat + x, 0u) ? ~0ull : atomicAdd(reinterpret_cast<unsigned long long*>(w.minc + x), 0ull);
+                }
                 if (!live && e.kind == kOpDirect) gave[e.slot] = 1;
             }
             any_merged = any_merged || __ballot(has && !live) != 0;
@@ -1053,8 +1116,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             for (uint32_t c0 = 0; c0 < m; c0 += 64) {
                 if (c0 + lane >= m) continue;
                 const Entry e = fetch_entry(w, b, c0 + lane);
-                const uint64_t x = set_slot(w, e.key);
-                const uint32_t last = atomicOr(&w.dd[x].last, 0u);
+                const uint32_t last = in_lds ? hl[slow_find(hk, e.key)] : atomicOr(&w.dd[set_slot(w, e.key)].last, 0u);
                 if (last == (uint32_t)e.w + 1u) continue;  // the key's winning entry
                 uint8_t s = 4;
                 if (e.kind == kOpUpdate) {
