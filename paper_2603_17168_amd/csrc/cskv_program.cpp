@@ -38,6 +38,7 @@ struct Segment {
     uint64_t total;      // keys in the run
     uint32_t desc_off;   // index of the run's first descriptor
     uint32_t last;       // last op of the run
+    uint32_t shape;      // the op whose launch shape the run takes: its largest batch
 };
 
 // Phases of the overlapped form.  A find run is one phase; an erase is probe (reader) + clear
@@ -159,14 +160,15 @@ static void build_plan(cskv_program* p) {
             if (open)
                 for (uint32_t h : p->hazards[i])
                     if (h >= p->segs.back().first) open = false;
-            if (!open) p->segs.push_back(Segment{kFind, i, 0, 0, (uint32_t)p->descs.size(), i});
+            if (!open) p->segs.push_back(Segment{kFind, i, 0, 0, (uint32_t)p->descs.size(), i, i});
             Segment& s = p->segs.back();
             p->descs.push_back(FindDesc{o.keys, o.out, o.flags, o.scores_out, s.total, o.n});
             s.count += 1;
             s.total += o.n;
             s.last = i;
+            if (o.n > p->ops[s.shape].n) s.shape = i;
         } else {
-            p->segs.push_back(Segment{o.kind, i, 1, o.n, 0, i});
+            p->segs.push_back(Segment{o.kind, i, 1, o.n, 0, i, i});
         }
     }
 }
@@ -439,7 +441,7 @@ uint32_t cskv_program_phases(const cskv_program* p) { return p ? (uint32_t)p->ph
 
 static int run_find_run(cskv_program* p, const Segment& g, hipStream_t s) {
     const cskv_table* t = p->table;
-    const Op& o = p->ops[g.first];
+    const Op& o = p->ops[g.shape];  // the largest batch of the run sets the shape
     const FindDesc* d = reinterpret_cast<const FindDesc*>(p->ws);
     const unsigned blocks = o.blocks_per_cu > 0 ? (unsigned)(o.blocks_per_cu * t->num_cus) : 0u;
     return launch_find_multi(t->view, d + g.desc_off, g.count, g.total, o.group, o.prefetch, blocks, s) == hipSuccess
