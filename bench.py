@@ -45,16 +45,16 @@ def log(*a):
 # `bench.py --counter-probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what the counter read
 # for a 1 GiB device copy in the same run; recorded for the find source with this SHA-256
 # (cskv_find.hip + cskv_device.h + cskv_internal.h) and reported only while that source is unchanged.
-FIND_TRAFFIC = {"source_sha256": "f6d274a46dd342e14f4ea676e5db3e8a2807a7b2674dad971dac47a3a85ada0d", "dim": 32,
-                "per_key": {"0.50": {"hit100": 602.7, "hit50": 460.8}, "0.75": {"hit100": 625.3, "hit50": 487.8},
-                            "0.90": {"hit100": 639.4, "hit50": 504.7}, "1.00": {"hit100": 650.1, "hit50": 516.3}}}
+FIND_TRAFFIC = {"source_sha256": "129c404e019d0fb53203bde7bd416a58a96a372e6d8db315bd20168eda3fb814", "dim": 32,
+                "per_key": {"0.50": {"hit100": 602.6, "hit50": 460.7}, "0.75": {"hit100": 625.4, "hit50": 487.8},
+                            "0.90": {"hit100": 639.3, "hit50": 504.6}, "1.00": {"hit100": 650.1, "hit50": 516.0}}}
 
 
 # The same two counter runs, summed over the kernels of one insert_or_assign call of 2^20 fresh keys
-# (fill, dedupe, route, apply, finish), bytes per key; recorded for the upsert sources with this
+# (dedupe with the scratch clear, route, commit, apply, finish), bytes per key; recorded for the upsert sources with this
 # SHA-256 (cskv_upsert.hip + cskv_kernels.hip + cskv_device.h + cskv_internal.h).
-UPSERT_TRAFFIC = {"source_sha256": "4f50f698e7369b1c0bbd6672992d398127c6d3ef5c6dcd4ac40a3a81077c1ac9", "dim": 32,
-                  "per_key": {"0.50": 1038.7, "0.75": 1070.5, "0.90": 1085.9, "1.00": 2102.2}}
+UPSERT_TRAFFIC = {"source_sha256": "ddd196cce3e305117d24d55c66a9a3c58a14eed3a7029bb925b81b2d08d949c5", "dim": 32,
+                  "per_key": {"0.50": 873.6, "0.75": 905.1, "0.90": 920.2, "1.00": 1939.1}}
 
 
 FIND_SOURCES = ("cskv_find.hip", "cskv_device.h", "cskv_internal.h")
