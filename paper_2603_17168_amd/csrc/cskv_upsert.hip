@@ -579,7 +579,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             nfree = gsum_i<GA>(__popc(taken));
         }
         full_after = nins >= nfree;
-        const int want = nins - nfree;  // inserts beyond the free slots: they compete for victims
+        int want = nins - nfree;  // inserts beyond the free slots: they compete for victims
+        // A full bucket that receives only inserts, none scoring above its cached minimum, refuses
+        // them all (strict admission) and keeps its minimum: its score and key lines are not read.
+        // (Under LRU a call's inserts always score above the residents.)
+        if (want > 0 && nfree == 0 && nu == 0 && t.policy != 1) {
+            const uint64_t top = ~gmin_u64<GA>(is_ins ? ~e.score : ~0ull);  // the best insert score
+            if (t.bmin[2 * (size_t)b + 1] != 0 && top <= t.bmin[2 * (size_t)b]) {
+                want = 0;
+                full_after = false;
+            }
+        }
         if (want > 0) {
             for (int x = 0; x < (int)m; ++x) {
                 const uint64_t sx = __shfl(e.score, x, GA);
