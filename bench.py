@@ -1038,19 +1038,34 @@ def main():
             r["insert_or_assign_subrounds4_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
             if lv.target < 1.0:
                 t.erase(fk4, erased_out=erased)
-            # insert_and_evict of fresh keys (every insert evicts at load 1), beside the plain
-            # insert_or_assign of the same shape (erased again below load 1)
+            # insert_and_evict of fresh keys (every insert evicts at load 1) beside insert_or_assign of
+            # the same keys: each call from the same table (a snapshot restored before it), median
+            # of 3 alternating pairs
             fk5 = gen_keys(870 + li, batch, 0, device=dev)
-            t.workspace(cskv.OP_INSERT_AND_EVICT, batch)  # grown before the timed call
+            t.workspace(cskv.OP_INSERT_AND_EVICT, batch)  # grown before the timed calls
+            snap, clk = t.storage.clone(), t.clock
+            ms_ie, ms_io = [], []
+            for _ in range(3):
+                for evict in (False, True):
+                    t.storage.copy_(snap)
+                    t.clock = clk
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    if evict:
+                        t.insert_and_evict(fk5, rows, out=ev_out)
+                    else:
+                        t.insert_or_assign(fk5, rows, status_out=status)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    (ms_ie if evict else ms_io).append(e0.elapsed_time(e1))
+            t.storage.copy_(snap)
+            t.clock = clk
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            t.insert_and_evict(fk5, rows, out=ev_out)
-            e1.record()
-            torch.cuda.synchronize()
-            r["insert_and_evict_bkvs"] = batch / e0.elapsed_time(e1) / 1e6
-            if lv.target < 1.0:
-                t.erase(fk5, erased_out=erased)
+            del snap
+            r["insert_and_evict_bkvs"] = batch / float(np.median(ms_ie)) / 1e6
+            r["insert_or_assign_same_state_bkvs"] = batch / float(np.median(ms_io)) / 1e6
+            r["insert_and_evict_vs_insert_or_assign"] = round(float(np.median(ms_io)) / float(np.median(ms_ie)), 3)
             # find_or_insert of half resident, half fresh keys; the fresh ones are erased again
             fk = torch.cat([q100[li][: batch // 2], gen_keys(850 + li, batch - batch // 2, 0, device=dev)])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
