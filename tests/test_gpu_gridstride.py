@@ -1,7 +1,8 @@
-"""Oracle parity on shapes that drive the kernels' grid-stride loops past their first pass: a
-launch grid is capped (fix-up pass, slow per-bucket apply, export), so only tables or batches
-larger than the cap make a block take a second tile.  Each case is checked against the oracle
-call by call and by whole-table exports (rows through value-ids)."""
+"""Oracle parity on shapes that only full-size runs would otherwise reach: launch grids that are
+capped (slow per-bucket apply, export), so that only tables or batches larger than the cap make
+a block take a second tile; keys repeated across many input blocks on a large table; and a
+bucket crowded with more distinct keys than the slow apply's LDS merge table holds.  Each case is
+checked against the oracle call by call and by whole-table exports (rows through value-ids)."""
 import sys
 
 import numpy as np
@@ -9,6 +10,7 @@ import pytest
 import torch
 
 from paper_2603_17168_amd.workload import as_u64, keys as gen_keys, permutation, uniform_u64
+from tests.hashkeys import keys_for
 from tests.parity import Twin
 
 pytestmark = pytest.mark.gpu
@@ -22,8 +24,8 @@ def say(*a):
 @pytest.mark.parametrize("policy", ["custom", "lfu", "lru"])
 def test_repeated_keys_on_2e17_buckets(policy):
     """2^24 slots (2^17 buckets): calls whose keys repeat (each distinct key 1-4 times, shuffled,
-    residents and fresh keys mixed), so that the pass handing every operation its key's last
-    occurrence covers more buckets than one pass of its grid."""
+    residents and fresh keys mixed), so that most repeated keys reach their bucket from several
+    input blocks and the apply merges their entries all over a large table."""
     cap = 1 << 24
     tw = Twin(cap, 4, "dual", policy, seed=51)
     base = as_u64(gen_keys(70, 1 << 18))
@@ -72,3 +74,28 @@ def test_export_beyond_one_grid():
     tw.erase(as_u64(gen_keys(120, 1 << 18)))
     tw.check_table()
     tw.export_if(2)
+
+
+@pytest.mark.parametrize("policy", ["custom", "lfu"])
+@pytest.mark.parametrize("distinct", [400, 600])
+def test_crowded_bucket_merge_table_and_fallback(policy, distinct):
+    """One bucket receives every key of the batch, each key from several blocks of 1024 input
+    positions, so the slow apply merges one entry per block and key: 400 distinct keys fit its LDS
+    merge table, 600 overflow it and merge through the call's dedupe set instead.  The bucket is
+    filled first, then takes the crowded batch with evictions, against the oracle."""
+    nb = 8
+    tw = Twin(nb * 128, 4, "single", policy, seed=54)
+    fill = np.array(keys_for(3, 3, nb, 128, salt0=1 << 12), dtype=np.uint64)
+    sc = np.arange(1, 129, dtype=np.uint64) * np.uint64(10)
+    tw.upsert(fill, sc if policy == "custom" else None)
+    ks = np.array(keys_for(3, 3, nb, distinct, salt0=1 << 13), dtype=np.uint64)
+    batch = np.concatenate([ks, ks[::-1], ks])  # every key in at least two input blocks
+    if policy == "custom":
+        scores = (as_u64(uniform_u64(130 + distinct, batch.size)) % np.uint64(2000)) + np.uint64(1)
+    else:
+        scores = (as_u64(uniform_u64(131 + distinct, batch.size)) % np.uint64(3)) + np.uint64(1)
+    say(f"crowded bucket, {policy}, {distinct} distinct keys in {batch.size} positions")
+    st = tw.upsert(batch, scores, evict=True)
+    assert (st == 3).sum() > 0 and (st == 4).sum() > 0
+    tw.check_table()
+    tw.find(np.concatenate([fill, ks]))
