@@ -194,7 +194,7 @@ def compare(label: str, g: dict, o: dict, seed: int, dim: int, dev):
         if not np.array_equal(g["found"], o["found"]):
             bad = np.nonzero(g["found"] != o["found"])[0]
             raise AssertionError(f"{label}: found mask differs at {bad[:8]} (gpu {g['found'][bad[:8]]}, "
-                                 f"oracle {o['found'][bad[:8]]}), {bad.size} of {bad.size and g['found'].size}")
+                                 f"oracle {o['found'][bad[:8]]}), {bad.size} of {g['found'].size}")
         if g["scores"] is not None:  # None: the call returned no scores
             assert np.array_equal(g["scores"], o["scores"]), f"{label}: found scores differ"
         assert _rows_equal(g["rows"], o["rows"], seed, dim, dev), f"{label}: found rows differ"
