@@ -3,7 +3,7 @@
 // Alg. 3 (score-based dual-bucket choice), under the deterministic batch order of cskv.h.
 //
 // A plain call (one route round) is a fixed sequence on one stream:
-//   dedupe   block-local, in LDS: each block of 1024 input positions keeps one representative per
+//   dedupe   block-local, in LDS: each block of 2048 input positions keeps one representative per
 //            key, its last occurrence in the block (and, for LFU, the block's sum of the key's
 //            increments); no global atomic per key.  The same launch clears the call's zeroed
 //            scratch (dedupe set, overflow keys, counters), which it does not read
@@ -134,14 +134,18 @@ __device__ __forceinline__ uint64_t set_slot(const UpsertWs& w, uint64_t k) {
 }
 
 // ------------------------------------------------------------------------------------------
-// block-local dedupe: 1024 input positions per 256-thread block, an LDS hash table of 2048 keys.
-// Each occurrence records the position of its key's last occurrence in the block (its
-// representative); a representative gets the block's (saturating) LFU sum of the key's increments.
-constexpr int kLocalKeys = 1024;
-constexpr int kLocalHash = 2048;
+// block-local dedupe: 2048 input positions per 512-thread block, an LDS hash table of 4096 keys
+// (48 KB; 96 KB with the LFU sums).  Each occurrence records the position of its key's last
+// occurrence in the block (its representative); a representative gets the block's (saturating)
+// LFU sum of the key's increments.  The larger the block, the fewer representatives a key that
+// repeats all over the batch sends to its bucket.
+constexpr int kLocalThreads = 512;
+constexpr int kLocalKeys = 2048;
+constexpr int kLocalHashBits = 12;
+constexpr int kLocalHash = 1 << kLocalHashBits;
 
 template <bool LFU>
-__global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
+__global__ void __launch_bounds__(kLocalThreads) k_local_dedupe(UpsertWs w, uint64_t n, const uint64_t* __restrict__ keys,
                                                       const uint64_t* __restrict__ scores, uint64_t* ev_count,
                                                       uint4* zero, size_t zero16) {
     __shared__ unsigned long long hk[kLocalHash];
@@ -149,7 +153,7 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
     __shared__ unsigned long long hi[LFU ? kLocalHash : 1];
     __shared__ uint32_t hs[LFU ? kLocalHash : 1];
     const int tid = threadIdx.x;
-    for (int j = tid; j < kLocalHash; j += 256) {
+    for (int j = tid; j < kLocalHash; j += kLocalThreads) {
         hk[j] = 0ull;
         hl[j] = 0u;
         if constexpr (LFU) {
@@ -159,21 +163,21 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
     }
     if (blockIdx.x == 0 && tid == 0 && ev_count) *ev_count = 0;
     // the call's zeroed scratch (dedupe set, overflow keys, counters), which this pass does not use
-    for (size_t z = (size_t)blockIdx.x * 256 + tid; z < zero16; z += (size_t)gridDim.x * 256)
+    for (size_t z = (size_t)blockIdx.x * kLocalThreads + tid; z < zero16; z += (size_t)gridDim.x * kLocalThreads)
         zero[z] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kLocalKeys;
-    constexpr int PER = kLocalKeys / 256;
+    constexpr int PER = kLocalKeys / kLocalThreads;
     int hslot[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const uint32_t li = (uint32_t)(q * 256 + tid);
+        const uint32_t li = (uint32_t)(q * kLocalThreads + tid);
         const uint64_t i = base + li;
         hslot[q] = -1;
         if (i >= n) continue;
         const uint64_t k = keys[i];
         if (reserved_key(k)) continue;
-        uint32_t h = (uint32_t)((fmix64(k) * kGold) >> (64 - 11));
+        uint32_t h = (uint32_t)((fmix64(k) * kGold) >> (64 - kLocalHashBits));
         for (int probes = 0; probes < kLocalHash; ++probes) {
             const unsigned long long old = atomicCAS(&hk[h], 0ull, (unsigned long long)k);
             if (old == 0ull) break;
@@ -191,7 +195,7 @@ __global__ void __launch_bounds__(256) k_local_dedupe(UpsertWs w, uint64_t n, co
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const uint64_t i = base + (uint32_t)(q * 256 + tid);
+        const uint64_t i = base + (uint32_t)(q * kLocalThreads + tid);
         if (i >= n) continue;
         if (hslot[q] < 0) {
             w.slot_of[i] = kNoSlot;
@@ -1304,9 +1308,9 @@ hipError_t launch_upsert(const TableView& t, const UpsertWs& w, uint64_t n, cons
     uint4* zero = reinterpret_cast<uint4*>(w.dd);  // the dedupe pass clears the scratch (a multiple of 256 bytes)
     const unsigned nblk = (unsigned)((n + kLocalKeys - 1) / kLocalKeys);
     if (t.policy == 2)
-        k_local_dedupe<true><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
+        k_local_dedupe<true><<<nblk, kLocalThreads, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
     else
-        k_local_dedupe<false><<<nblk, 256, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
+        k_local_dedupe<false><<<nblk, kLocalThreads, 0, s>>>(wl, n, keys, scores, ev.count, zero, zero_bytes / 16);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_upsert_route(t, wl, n, keys, vals, scores, group, s)) != hipSuccess) return e;
     if ((e = launch_upsert_apply(t, wl, n, vals, ev, s)) != hipSuccess) return e;
