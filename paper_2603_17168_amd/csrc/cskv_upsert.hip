@@ -584,14 +584,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         }
         full_after = nins >= nfree;
         int want = nins - nfree;  // inserts beyond the free slots: they compete for victims
-        // A full bucket that receives only inserts, none scoring above its cached minimum, refuses
-        // them all (strict admission) and keeps its minimum: its score and key lines are not read.
-        // (Under LRU a call's inserts always score above the residents.)
-        if (want > 0 && nfree == 0 && nu == 0 && t.policy != 1) {
-            const uint64_t top = ~gmin_u64<GA>(is_ins ? ~e.score : ~0ull);  // the best insert score
-            if (t.bmin[2 * (size_t)b + 1] != 0 && top <= t.bmin[2 * (size_t)b]) {
-                want = 0;
-                full_after = false;
+        // A bucket that was full keeps its cached minimum (score, key) when every update leaves that
+        // entry the smallest (no update of the minimum's own key, none to a smaller pair) and no
+        // insert scores above it (strict admission refuses them all): then its score and key lines
+        // are not read and its cached minimum stands.  (Under LRU a call's inserts always score above
+        // the residents, so only buckets without inserts are checked.)
+        if (nfree == 0 && (want == 0 || t.policy != 1)) {
+            const uint64_t ms = t.bmin[2 * (size_t)b], mk = t.bmin[2 * (size_t)b + 1];
+            if (mk != 0) {
+                const bool keeps = !is_upd || (e.key != mk && (e.score > ms || (e.score == ms && e.key > mk)));
+                const bool kept = ((__ballot(!keeps) >> gshift) & 0xFFFFu) == 0u;
+                const uint64_t top = ~gmin_u64<GA>(is_ins ? ~e.score : ~0ull);  // the best insert score
+                if (kept && (want == 0 || top <= ms)) {
+                    want = 0;
+                    full_after = false;
+                }
             }
         }
         if (want > 0) {
