@@ -354,3 +354,80 @@ def test_launch_shapes_do_not_change_results():
         tw.check_table()
     with pytest.raises(cskv.CskvError):
         tw.gpu.set_tuning(find_group=5)
+
+
+@pytest.mark.parametrize("policy", ["custom", "lfu", "lru"])
+def test_cached_minimum_after_update_only_calls(policy):
+    """A full bucket's cached minimum (score, key) through calls the apply may finish without
+    reading the bucket's lines: updates that leave the minimum the smallest entry, updates of the
+    minimum's own key, (CUSTOM) updates to a smaller score or to the minimum's score with a
+    smaller key, and calls whose inserts cannot beat the minimum.  After each call one insert that
+    just beats the true minimum shows which entry the table evicts; everything against the oracle."""
+    nb = 4
+    tw = Twin(nb * 128, 8, "dual", policy, seed=17)
+    salt = [1 << 16]
+
+    def fresh(n):
+        k = np.array([key_for(1, 1, nb, salt=salt[0] + i) for i in range(n)], dtype=np.uint64)
+        salt[0] += n
+        return k
+
+    def bucket():
+        k, _, s, _ = tw.ora.export()
+        return k, s
+
+    def minimum():
+        k, s = bucket()
+        o = np.lexsort((k, s))
+        return k[o[0]], s[o[0]], k[o[1]]
+
+    def sc(vals):
+        return None if policy == "lru" else np.asarray(vals, dtype=np.uint64)
+
+    fill = fresh(128)
+    tw.upsert(fill, sc(np.arange(100, 228) if policy == "custom" else np.ones(128)))
+    tw.check_table()
+
+    def probe():
+        # one insert scoring just above the minimum evicts exactly the minimum
+        mk, ms, _ = minimum()
+        tw.upsert(fresh(1), sc([int(ms) + 1]), evict=True)
+        tw.check_table()
+
+    for step in range(4):
+        mk, ms, second = minimum()
+        k, s = bucket()
+        other = k[(k != mk) & (k != second)][step]
+        # an update that leaves the minimum the smallest entry
+        tw.upsert(np.array([other], dtype=np.uint64), sc([int(ms) + 50]))
+        tw.check_table()
+        probe()
+        # an update of the minimum's own key
+        mk, ms, _ = minimum()
+        tw.upsert(np.array([mk], dtype=np.uint64), sc([int(ms) + 7]))
+        tw.check_table()
+        probe()
+        if policy == "custom":
+            # a resident lowered below the minimum, then one set to the minimum's score with a smaller key
+            mk, ms, _ = minimum()
+            k, s = bucket()
+            tw.upsert(np.array([k[k != mk][0]], dtype=np.uint64), sc([max(int(ms) - 3, 1)]))
+            tw.check_table()
+            probe()
+            mk, ms, _ = minimum()
+            k, s = bucket()
+            smaller = k[k < mk]
+            if smaller.size:
+                tw.upsert(np.array([smaller[0]], dtype=np.uint64), sc([int(ms)]))
+                tw.check_table()
+                probe()
+        # inserts that cannot beat the minimum, beside an update of another resident
+        mk, ms, _ = minimum()
+        k, s = bucket()
+        weak = fresh(3)
+        if policy == "lru":
+            tw.upsert(np.concatenate([weak, k[k != mk][:1]]), None, evict=True)  # LRU inserts always win
+        else:
+            tw.upsert(np.concatenate([weak, k[k != mk][:1]]), sc([int(ms)] * 3 + [int(ms) + 9]), evict=True)
+        tw.check_table()
+        probe()
