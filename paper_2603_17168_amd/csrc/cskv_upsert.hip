@@ -20,8 +20,9 @@
 //            repeated across blocks all land in the same bucket's list.
 //            Routing also writes each representative's status as far as it knows it (UPDATED,
 //            INSERTED for a direct insert).
-//   commit   one thread per bucket: a bucket that received only direct inserts of distinct keys
-//            and keeps a free slot is finished by writing their digest bytes
+//   commit   (calls of more than 16384 keys) one thread per bucket: a bucket that received only
+//            direct inserts of distinct keys and keeps a free slot is finished by writing their
+//            digest bytes
 //   apply    16 lanes per bucket (8 slots each), 16 buckets per 256-thread block, for the buckets
 //            the commit left.  The entries of one key are merged first: the one with the largest
 //            input position (the key's last occurrence) wins, LFU increments are summed.  A bucket
@@ -443,7 +444,8 @@ __global__ void __launch_bounds__(256) k_route(TableView t, UpsertWs w, uint64_t
 // that fills up, more than 16 operations, find_or_insert) is left to the apply kernels, which
 // rewrite all its statuses.  A bucket whose cached minimum is set was full when last written and
 // most likely still is, so its entries are not read.
-constexpr int kLiteMax = 8;  // operations of a bucket that one thread commits
+constexpr int kLiteMax = 8;                 // operations of a bucket that one thread commits
+constexpr uint64_t kCommitMinKeys = 16384;  // calls with fewer keys skip the commit pass
 
 __global__ void __launch_bounds__(256) k_apply_commit(TableView t, UpsertWs w) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1264,7 +1266,9 @@ hipError_t launch_upsert_apply(const TableView& t, const UpsertWs& w, uint64_t n
                                hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint64_t visit = w.list_mode ? (n < t.nbuckets ? n : t.nbuckets) : t.nbuckets;
-    k_apply_commit<<<(unsigned)((visit + 255) / 256), 256, 0, s>>>(t, w);
+    // the one-thread commit pays off once the touched buckets are many; below that the fast apply
+    // finishes plain buckets itself and the call saves a launch
+    if (n > kCommitMinKeys) k_apply_commit<<<(unsigned)((visit + 255) / 256), 256, 0, s>>>(t, w);
     k_apply_fast<<<(unsigned)((visit + kApplyGroups - 1) / kApplyGroups), 256, 0, s>>>(t, w, vals, ev);
     uint64_t slow_blocks = n < t.nbuckets ? n : t.nbuckets;
     if (slow_blocks > 2048) slow_blocks = 2048;
