@@ -26,7 +26,9 @@ extern "C" {
 #endif
 
 /* Copies `bytes` (a multiple of 16) from d_src to d_dst (both 16-byte aligned, not overlapping)
- * with one 16-byte load and one 16-byte store per lane per grid-stride step. */
+ * with one 16-byte load and one 16-byte store per lane, one lane per 16 bytes.  CSKV_EINVAL for
+ * misaligned or null pointers, a size that is not a multiple of 16, or more than 2^31 - 1 blocks
+ * of 256 lanes (over 8 TiB). */
 int cskv_probe_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
 
 /* n random gathers: access i reads `width` bytes (8, 16, 32, 64 or 128) at the width-aligned
