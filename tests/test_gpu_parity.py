@@ -170,7 +170,7 @@ def test_ragged_batch_sizes(n, pairs):
     tw.check_table()
 
 
-@pytest.mark.parametrize("dim", [4, 8, 32, 64, 128, 132])
+@pytest.mark.parametrize("dim", [4, 8, 32, 64, 128, 132, 1020, 1024])
 def test_value_dims(dim):
     say(f"dim {dim}")
     tw = Twin(32 * 128, dim, "dual", "custom", seed=dim)
