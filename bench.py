@@ -206,7 +206,7 @@ def calibrate_granule(dev, gib: int = 4, n: int = 1 << 24, reps: int = 5) -> dic
 
 
 def upsert_bytes_contract(dim: int, load: float, hist: dict) -> float:
-    """Bytes per key of an upsert call in the survey's contract model, weighted by the call's
+    """Bytes per key of an upsert call in the hot-path contract's model, weighted by the call's
     status histogram {status: count} (fresh keys: no updates).  It charges phase D2 both buckets'
     whole score lines per key, as Alg. 3 read literally does:
     INSERT        = key + row + both digest lines + false-positive key granules (load)
