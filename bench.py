@@ -855,8 +855,8 @@ def main():
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a table lives on one device; "
+              "sharding keys over several tables is left to the caller); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.cpu_baseline_worker:
         cpu_baseline_worker(args.log2_capacity, args.log2_batch, [float(x) for x in args.loads.split(",")],
