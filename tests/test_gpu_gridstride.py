@@ -79,7 +79,7 @@ def test_export_beyond_one_grid():
 @pytest.mark.parametrize("policy", ["custom", "lfu"])
 @pytest.mark.parametrize("distinct", [400, 600])
 def test_crowded_bucket_merge_table_and_fallback(policy, distinct):
-    """One bucket receives every key of the batch, each key from several blocks of 1024 input
+    """One bucket receives every key of the batch, each key from several blocks of 2048 input
     positions, so the slow apply merges one entry per block and key: 400 distinct keys fit its LDS
     merge table, 600 overflow it and merge through the call's dedupe set instead.  The bucket is
     filled first, then takes the crowded batch with evictions, against the oracle."""
@@ -89,7 +89,8 @@ def test_crowded_bucket_merge_table_and_fallback(policy, distinct):
     sc = np.arange(1, 129, dtype=np.uint64) * np.uint64(10)
     tw.upsert(fill, sc if policy == "custom" else None)
     ks = np.array(keys_for(3, 3, nb, distinct, salt0=1 << 13), dtype=np.uint64)
-    batch = np.concatenate([ks, ks[::-1], ks])  # every key in at least two input blocks
+    reps = 12 if distinct == 400 else 8  # 4800 positions: every key in at least two input blocks
+    batch = np.concatenate([ks if r % 2 == 0 else ks[::-1] for r in range(reps)])
     if policy == "custom":
         scores = (as_u64(uniform_u64(130 + distinct, batch.size)) % np.uint64(2000)) + np.uint64(1)
     else:
