@@ -828,6 +828,18 @@ constexpr int kSlowKeys = 512;
 
 __device__ __forceinline__ uint32_t slow_hash(uint64_t k) { return (uint32_t)((fmix64(k) * kGold) >> (64 - 9)); }
 
+// A crowded bucket's list positions past the inline ones live in the hashed overflow table; the
+// merge pass finds their slots (the probes of 8 positions per lane issued together) and keeps them
+// in LDS for the bucket's later passes, which then load each entry with one access.
+constexpr int kSlowBatch = 8;
+constexpr uint32_t kSlowStage = 1024;
+
+__device__ __forceinline__ Entry staged_entry(const UpsertWs& w, uint32_t b, uint32_t r, const uint32_t* qst, bool staged) {
+    if (r < w.cap) return load_entry(w.il + (size_t)b * w.cap + r);
+    if (staged) return load_entry(w.ol + qst[r]);
+    return fetch_entry(w, b, r);
+}
+
 // the merge-table slot of key k, claimed if new; -1 if the table is full
 __device__ __forceinline__ int slow_claim(unsigned long long* hk, uint64_t k) {
     uint32_t h = slow_hash(k);
@@ -861,6 +873,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
     __shared__ uint8_t rslot[128], dslot[128], uflag[128], nflag[128], gave[128], plist[128];
     __shared__ uint64_t newk[128], news[128];
     __shared__ unsigned long long ev_base_s;
+    __shared__ uint32_t qst[kSlowStage];            // overflow-table slots of the list positions
 
     const int lane = threadIdx.x;
     // routing has read the clock (every sub-round of the call reads the same value)
@@ -891,6 +904,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         // bucket has more distinct keys than it holds, through the call's dedupe set
         bool any_merged = false;
         bool in_lds = true;
+        const bool staged = w.local && m <= kSlowStage;
         if (w.local) {
             for (int j = lane; j < kSlowKeys; j += 64) {
                 hk[j] = 0ull;
@@ -900,18 +914,50 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             }
             if (lane == 0) hfull = 0;
             __syncthreads();
-            for (uint32_t c0 = 0; c0 < m; c0 += 64) {
-                if (c0 + lane >= m) continue;
-                const Entry e = fetch_entry(w, b, c0 + lane);
-                const int x = slow_claim(hk, e.key);
-                if (x < 0) {
-                    hfull = 1;
-                    continue;
+            for (uint32_t c0 = 0; c0 < m; c0 += 64 * kSlowBatch) {
+                uint64_t q[kSlowBatch], got[kSlowBatch];
+#pragma unroll
+                for (int u = 0; u < kSlowBatch; ++u) {  // first probes of every overflow position
+                    const uint32_t r = c0 + 64 * u + lane;
+                    q[u] = 0;
+                    got[u] = 0;
+                    if (r < m && r >= w.cap) {
+                        q[u] = scratch_hash(overflow_key(b, r), w.logP);
+                        got[u] = w.okey[q[u]];
+                    }
                 }
-                atomicMax(&hl[x], (uint32_t)e.w + 1u);
-                if (t.policy == 2) {
-                    const unsigned long long old = atomicAdd(&hi[x], (unsigned long long)e.score);
-                    if (old + e.score < old) atomicOr(&hs[x], 1u);
+                Entry eu[kSlowBatch];
+#pragma unroll
+                for (int u = 0; u < kSlowBatch; ++u) {
+                    const uint32_t r = c0 + 64 * u + lane;
+                    eu[u] = Entry{0, 0, 0, 0, 0, kOpUpdate, 0};
+                    if (r >= m) continue;
+                    if (r < w.cap) {
+                        eu[u] = load_entry(w.il + (size_t)b * w.cap + r);
+                        continue;
+                    }
+                    const uint64_t ok = overflow_key(b, r);
+                    for (uint64_t probes = 0; probes < w.P && got[u] != ok; ++probes) {
+                        q[u] = (q[u] + 1) & (w.P - 1);
+                        got[u] = w.okey[q[u]];
+                    }
+                    if (staged) qst[r] = (uint32_t)q[u];
+                    eu[u] = load_entry(w.ol + q[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < kSlowBatch; ++u) {
+                    if (c0 + 64 * u + lane >= m) continue;
+                    const Entry& e = eu[u];
+                    const int x = slow_claim(hk, e.key);
+                    if (x < 0) {
+                        hfull = 1;
+                        continue;
+                    }
+                    atomicMax(&hl[x], (uint32_t)e.w + 1u);
+                    if (t.policy == 2) {
+                        const unsigned long long old = atomicAdd(&hi[x], (unsigned long long)e.score);
+                        if (old + e.score < old) atomicOr(&hs[x], 1u);
+                    }
                 }
             }
             __syncthreads();
@@ -919,7 +965,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
             if (!in_lds) {
                 for (uint32_t c0 = 0; c0 < m; c0 += 64) {
                     if (c0 + lane >= m) continue;
-                    const Entry e = fetch_entry(w, b, c0 + lane);
+                    const Entry e = staged_entry(w, b, c0 + lane, qst, staged);
                     const uint64_t x = set_slot(w, e.key);
                     atomicMax(&w.dd[x].last, (uint32_t)e.w + 1u);
                     if (t.policy == 2) {
@@ -939,7 +985,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         for (uint32_t c0 = 0; c0 < m; c0 += 64) {
             const bool has = c0 + lane < m;
             Entry e{0, 0, 0, 0, 0, kOpUpdate, 0};
-            if (has) e = fetch_entry(w, b, c0 + lane);
+            if (has) e = staged_entry(w, b, c0 + lane, qst, staged);
             bool live = has;
             if (has && w.local) {
                 if (in_lds) {
@@ -1138,7 +1184,7 @@ __global__ void __launch_bounds__(64) k_apply_slow(TableView t, UpsertWs w, cons
         if (any_merged) {
             for (uint32_t c0 = 0; c0 < m; c0 += 64) {
                 if (c0 + lane >= m) continue;
-                const Entry e = fetch_entry(w, b, c0 + lane);
+                const Entry e = staged_entry(w, b, c0 + lane, qst, staged);
                 const uint32_t last = in_lds ? hl[slow_find(hk, e.key)] : atomicOr(&w.dd[set_slot(w, e.key)].last, 0u);
                 if (last == (uint32_t)e.w + 1u) continue;  // the key's winning entry
                 uint8_t s = 4;
