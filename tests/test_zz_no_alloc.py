@@ -89,6 +89,33 @@ def test_noalloc_equals_workspace_entry_point(policy, cap):
         pool = as_u64(k.cpu())
 
 
+@pytest.mark.parametrize("policy", ["lru", "lfu"])
+def test_noalloc_with_route_subrounds(policy):
+    """Route sub-rounds (the call's keys applied in 4 chunks) take the global-dedupe path with its
+    rank arrays, which the fixed array must also hold: same results as the workspace entry point
+    on two calls, the second smaller."""
+    dev = torch.device("cuda:0")
+    ref = cskv.Table(1 << 15, 8, mode="dual", policy=policy)
+    ref.set_route_subrounds(4)
+    k0, v0, s0 = batch(500, 20000, None, policy, dev)
+    ref.insert_or_assign(k0, v0, s0, want_status=False)
+    torch.cuda.synchronize()
+    got = clone(ref)
+    got.set_route_subrounds(4)
+    pool = as_u64(k0.cpu())
+    for call, n in enumerate([cskv.NOALLOC_MAX_KEYS, 3000]):
+        k, v, s = batch(510 + 10 * call, n, pool, policy, dev)
+        say(f"noalloc sub-rounds {policy} call {call}: n {k.numel()}")
+        st_ref = ref.insert_or_assign(k, v, s)
+        st = torch.full((k.numel(),), 0xEE, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        got.insert_or_assign_noalloc(k, v, s, status_out=st)
+        torch.cuda.synchronize()
+        assert torch.equal(st, st_ref)
+        assert_same_table(got, ref)
+        pool = as_u64(k.cpu())
+
+
 def test_noalloc_refuses_batches_above_the_limit():
     dev = torch.device("cuda:0")
     t = cskv.Table(1 << 14, 8, mode="dual", policy="lru")
